@@ -1,0 +1,174 @@
+/*
+ * Plain CPU oracle for the skew-layout join-aggregate path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load or call this code; the product path
+ * never does.  It shares no source with the GPU library.
+ *
+ * Everything here is the plain definition, written as one ordered loop per
+ * step, in 64-bit integers (no floating point).  Where the paper leaves a
+ * detail open, the reading taken is stated next to the code:
+ *   - keys are 0-based offsets into the dimension table (the paper's figure
+ *     counts from 1);
+ *   - keys with equal frequency are ordered by ascending key, so the
+ *     permutation index is unique;
+ *   - keys that never occur in the fact column still get a position: they
+ *     come last, in ascending key order, so the permuted dimension keeps
+ *     every row.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/*
+ * Frequency of every dimension key in the fact column C: the aggregation
+ * query that starts index building (Section 3.1; Q3 of Section 1).
+ * Keys outside [0, n_keys) are not counted; their number is returned.
+ */
+int64_t oracle_key_counts(const int32_t *C, int64_t n_fact, int32_t n_keys, int64_t *cnt) {
+  int64_t invalid = 0;
+  for (int32_t k = 0; k < n_keys; ++k) cnt[k] = 0;
+  for (int64_t j = 0; j < n_fact; ++j) {
+    const int32_t k = C[j];
+    if (k < 0 || k >= n_keys) {
+      ++invalid;
+      continue;
+    }
+    cnt[k] += 1;
+  }
+  return invalid;
+}
+
+typedef struct {
+  int64_t cnt;
+  int32_t key;
+} freq_entry;
+
+/* Decreasing frequency; equal frequencies by ascending key. */
+static int by_decreasing_frequency(const void *pa, const void *pb) {
+  const freq_entry *a = (const freq_entry *)pa, *b = (const freq_entry *)pb;
+  if (a->cnt != b->cnt) return a->cnt > b->cnt ? -1 : 1;
+  return (a->key > b->key) - (a->key < b->key);
+}
+
+/*
+ * Permutation index (Section 3, Fig. 2a): the keys listed in decreasing
+ * frequency order, perm[r] = key of rank r.  Its rank representation
+ * (Fig. 2b) is the inverse, rank[perm[r]] = r; both are kept so lookups in
+ * either direction are O(1) (Section 3).  Sorting the small key domain by
+ * frequency is the second step of index building (Section 3.1).
+ */
+void oracle_permutation_index(const int64_t *cnt, int32_t n_keys, int32_t *perm, int32_t *rank) {
+  freq_entry *e = (freq_entry *)malloc(sizeof(freq_entry) * (size_t)(n_keys > 0 ? n_keys : 1));
+  for (int32_t k = 0; k < n_keys; ++k) {
+    e[k].cnt = cnt[k];
+    e[k].key = k;
+  }
+  qsort(e, (size_t)n_keys, sizeof(freq_entry), by_decreasing_frequency);
+  for (int32_t r = 0; r < n_keys; ++r) perm[r] = e[r].key;
+  for (int32_t r = 0; r < n_keys; ++r) rank[perm[r]] = r;
+  free(e);
+}
+
+/*
+ * Recoding of the fact column (Section 3.1, Fig. 2c -> 2d): every reference
+ * to dimension row i is replaced by a reference to row Rank(i).  A key
+ * outside [0, n_keys) is copied unchanged.
+ */
+void oracle_recode(const int32_t *C, int64_t n_fact, const int32_t *rank, int32_t n_keys, int32_t *C_new) {
+  for (int64_t j = 0; j < n_fact; ++j) {
+    const int32_t k = C[j];
+    C_new[j] = (k >= 0 && k < n_keys) ? rank[k] : k;
+  }
+}
+
+/*
+ * Copy of a dimension column in permutation-index order (Section 3.2):
+ * out[r] = col[perm[r]].
+ */
+void oracle_permute_i32(const int32_t *col, const int32_t *perm, int32_t n_keys, int32_t *out) {
+  for (int32_t r = 0; r < n_keys; ++r) out[r] = col[perm[r]];
+}
+
+void oracle_permute_i8(const int8_t *col, const int32_t *perm, int32_t n_keys, int8_t *out) {
+  for (int32_t r = 0; r < n_keys; ++r) out[r] = col[perm[r]];
+}
+
+/*
+ * Foreign-key join followed by aggregation (Q1 and Q2 of Section 1 feeding a
+ * SUM/COUNT): for each fact row j in order, the dimension row k = C[j] is
+ * looked up by array offset (Section 2.2); it qualifies when its category is
+ * below cat_lt (signed 8-bit compare).  With by_category = 0 every qualifying
+ * row adds to group 0; otherwise it adds to group category, and rows whose
+ * category lies outside [0, 16) belong to no group.  Fact keys outside
+ * [0, n_rows) join nothing.  Sums and counts are exact 64-bit integers.
+ * n_groups outputs are written: 1, or 16 when by_category is set.
+ */
+void oracle_fk_join_aggregate(const int32_t *C, int64_t n_fact, const int32_t *price, const int8_t *category,
+                              int32_t n_rows, int32_t cat_lt, int32_t by_category, int64_t *sum,
+                              int64_t *count) {
+  const int n_groups = by_category ? 16 : 1;
+  for (int g = 0; g < n_groups; ++g) {
+    sum[g] = 0;
+    count[g] = 0;
+  }
+  for (int64_t j = 0; j < n_fact; ++j) {
+    const int32_t k = C[j];
+    if (k < 0 || k >= n_rows) continue;
+    const int32_t c = category[k];
+    if (!(c < cat_lt)) continue;
+    int g = 0;
+    if (by_category) {
+      if (c < 0 || c >= 16) continue;
+      g = c;
+    }
+    sum[g] += (int64_t)price[k];
+    count[g] += 1;
+  }
+}
+
+/*
+ * Grouped aggregation (Q3 of Section 1, with a SUM next to the COUNT):
+ * sum[g] = sum of V[j] over rows with G[j] = g, count[g] = number of such
+ * rows, for g in [0, n_groups).  Rows whose key is outside [0, n_groups)
+ * are skipped; their number is returned.
+ */
+int64_t oracle_group_aggregate(const int32_t *G, const int32_t *V, int64_t n_fact, int32_t n_groups, int64_t *sum,
+                               int64_t *count) {
+  int64_t invalid = 0;
+  for (int32_t g = 0; g < n_groups; ++g) {
+    sum[g] = 0;
+    count[g] = 0;
+  }
+  for (int64_t j = 0; j < n_fact; ++j) {
+    const int32_t g = G[j];
+    if (g < 0 || g >= n_groups) {
+      ++invalid;
+      continue;
+    }
+    sum[g] += (int64_t)V[j];
+    count[g] += 1;
+  }
+  return invalid;
+}
+
+/*
+ * The whole index build of Section 3.1 / 3.2 in the paper's order: count,
+ * sort by frequency, invert, recode the fact column, and copy the dimension
+ * columns in the new order.  counts_by_rank[r] = frequency of perm[r].
+ * price/category (and their outputs) may be NULL when the dimension has no
+ * columns to copy.  Returns the number of out-of-range keys.
+ */
+int64_t oracle_build_layout(const int32_t *C, int64_t n_fact, int32_t n_keys, const int32_t *price,
+                            const int8_t *category, int32_t *perm, int32_t *rank, int64_t *counts_by_rank,
+                            int32_t *C_new, int32_t *price_new, int8_t *category_new) {
+  int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_keys > 0 ? n_keys : 1));
+  const int64_t invalid = oracle_key_counts(C, n_fact, n_keys, cnt);
+  oracle_permutation_index(cnt, n_keys, perm, rank);
+  for (int32_t r = 0; r < n_keys; ++r) counts_by_rank[r] = cnt[perm[r]];
+  oracle_recode(C, n_fact, rank, n_keys, C_new);
+  if (price && price_new) oracle_permute_i32(price, perm, n_keys, price_new);
+  if (category && category_new) oracle_permute_i8(category, perm, n_keys, category_new);
+  free(cnt);
+  return invalid;
+}

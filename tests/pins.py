@@ -1,0 +1,242 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+Each function raises AssertionError when the oracle module it is given
+disagrees with an independent statement of the result: brute force on tiny
+tables, the paper's worked example, closed forms, invariants.  The same
+functions run against the real oracle (tests/test_oracle_pins.py) and against
+copies of it with planted mistakes (tests/test_oracle_mutants.py), which must
+each fail at least one pin.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+# ---------------------------------------------------------------------------
+# Brute force definitions (Python loops, tiny inputs only)
+# ---------------------------------------------------------------------------
+def nested_loop_join_aggregate(fact, dim_rows, cat_lt, by_category):
+    """SUM(price), COUNT(*) over Sales JOIN Dim ON key, WHERE category < cat_lt.
+
+    dim_rows is a list of (key, price, category) tuples in arbitrary storage
+    order: the join matches key values, it never uses a key as an offset.
+    """
+    g = 16 if by_category else 1
+    s = [0] * g
+    c = [0] * g
+    for fk in fact:
+        for key, price, cat in dim_rows:
+            if key != fk:
+                continue
+            if not (cat < cat_lt):
+                continue
+            grp = 0
+            if by_category:
+                if not (0 <= cat < 16):
+                    continue
+                grp = cat
+            s[grp] += int(price)
+            c[grp] += 1
+    return s, c
+
+
+def dict_group_aggregate(G, V, n_groups):
+    s = {}
+    c = {}
+    for g, v in zip(G, V):
+        g = int(g)
+        if 0 <= g < n_groups:
+            s[g] = s.get(g, 0) + int(v)
+            c[g] = c.get(g, 0) + 1
+    return [s.get(g, 0) for g in range(n_groups)], [c.get(g, 0) for g in range(n_groups)]
+
+
+def brute_force_order(fact, n_keys):
+    """Among all n_keys! orders, the one whose (-frequency, key) sequence is sorted."""
+    freq = [0] * n_keys
+    for k in fact:
+        freq[int(k)] += 1
+    best = None
+    for order in itertools.permutations(range(n_keys)):
+        seq = [(-freq[k], k) for k in order]
+        if all(seq[i] <= seq[i + 1] for i in range(n_keys - 1)):
+            assert best is None, "two sorted orders cannot exist for distinct keys"
+            best = list(order)
+    return best
+
+
+# ---------------------------------------------------------------------------
+# Pins
+# ---------------------------------------------------------------------------
+def pin_fk_bruteforce(orc, seeds=range(12)):
+    for seed in seeds:
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(1, 9))
+        f = int(rng.integers(0, 17))
+        price = rng.integers(-50, 10000, n).astype(np.int32)
+        cat = rng.integers(-3, 19, n).astype(np.int8)
+        fact = rng.integers(-1, n + 1, f).astype(np.int32)  # includes out-of-range keys
+        order = rng.permutation(n)
+        rows = [(int(k), int(price[k]), int(cat[k])) for k in order]
+        for cat_lt in (-128, 0, 4, 16, 127):
+            for by in (False, True):
+                s, c = orc.fk_join_aggregate(fact, price, cat, cat_lt, by)
+                bs, bc = nested_loop_join_aggregate(fact.tolist(), rows, cat_lt, by)
+                assert s.tolist() == bs and c.tolist() == bc, (seed, cat_lt, by)
+
+
+def pin_fk_special_cases(orc):
+    rng = np.random.default_rng(7)
+    # N = 1: every fact joins the single row, sum = F * price[0]
+    for F in (0, 1, 5, 1000):
+        fact = np.zeros(F, dtype=np.int32)
+        s, c = orc.fk_join_aggregate(fact, np.array([37], np.int32), np.array([2], np.int8), 4, False)
+        assert s[0] == 37 * F and c[0] == F
+        s, c = orc.fk_join_aggregate(fact, np.array([37], np.int32), np.array([9], np.int8), 4, False)
+        assert s[0] == 0 and c[0] == 0
+    # F = 0: all zeros
+    s, c = orc.fk_join_aggregate(np.zeros(0, np.int32), np.arange(5, dtype=np.int32),
+                                 np.arange(5, dtype=np.int8), 16, True)
+    assert not s.any() and not c.any()
+    # no filter and categories in [0, 16): group counts sum to F; cat_lt = 16 equals no filter
+    n, F = 50, 3000
+    price = rng.integers(1, 10001, n).astype(np.int32)
+    cat = rng.integers(0, 16, n).astype(np.int8)
+    fact = rng.integers(0, n, F).astype(np.int32)
+    s16, c16 = orc.fk_join_aggregate(fact, price, cat, 16, True)
+    s127, c127 = orc.fk_join_aggregate(fact, price, cat, 127, True)
+    assert c16.sum() == F and (s16 == s127).all() and (c16 == c127).all()
+    assert s16.sum() == int(price[fact].astype(np.int64).sum())
+    # filter cat < 4 without grouping equals the sum of groups 0..3
+    s4, c4 = orc.fk_join_aggregate(fact, price, cat, 4, False)
+    assert s4[0] == s16[:4].sum() and c4[0] == c16[:4].sum()
+
+
+def pin_group_bruteforce(orc, seeds=range(10)):
+    for seed in seeds:
+        rng = np.random.default_rng(100 + seed)
+        m = int(rng.integers(1, 12))
+        f = int(rng.integers(0, 40))
+        G = rng.integers(-1, m + 1, f).astype(np.int32)
+        V = rng.integers(-2**31, 2**31, f, dtype=np.int64).astype(np.int32)
+        s, c, inv = orc.group_aggregate(G, V, m)
+        bs, bc = dict_group_aggregate(G.tolist(), V.tolist(), m)
+        assert s.tolist() == bs and c.tolist() == bc, seed
+        assert inv == int(((G < 0) | (G >= m)).sum())
+
+
+def pin_layout_bruteforce(orc):
+    # every fact column over N = 3 keys with F = 4 rows (81 columns)
+    for fact in itertools.product(range(3), repeat=4):
+        fact = np.array(fact, dtype=np.int32)
+        L = orc.build_layout(fact, 3)
+        assert L.perm.tolist() == brute_force_order(fact.tolist(), 3), fact
+    # random columns for N up to 6, including keys that never occur
+    for seed in range(40):
+        rng = np.random.default_rng(200 + seed)
+        n = int(rng.integers(1, 7))
+        f = int(rng.integers(0, 12))
+        fact = rng.integers(0, n, f).astype(np.int32)
+        L = orc.build_layout(fact, n)
+        assert L.perm.tolist() == brute_force_order(fact.tolist(), n), (seed, fact)
+
+
+def pin_fig2(orc):
+    d = json.load(open(os.path.join(GOLDEN, "fig2_permutation_index.json")))
+    fact = np.array(d["fact_column_1based"], dtype=np.int32) - 1
+    letters = d["dimension_rows_1based"]
+    n = len(letters)
+    # the dimension's first column holds the letters; use their code points as int32 values
+    col = np.array([ord(x) for x in letters], dtype=np.int32)
+    L = orc.build_layout(fact, n, price=col)
+    assert [int(k) + 1 for k in L.perm[:4]] == d["paper_first_four_keys_1based"]
+    assert [chr(v) for v in L.price] == d["paper_permuted_dimension"]
+    assert L.perm.tolist() == d["expected_perm_0based"]
+    assert L.rank.tolist() == d["expected_rank_0based"]
+    # the most frequent key is recoded to 0 and so on (Fig. 2c -> 2d)
+    assert (L.fact_recoded == np.array(d["expected_rank_0based"])[fact]).all()
+
+
+def check_layout_invariants(L, fact, n_keys, price=None, category=None):
+    perm, rank = L.perm, L.rank
+    assert sorted(perm.tolist()) == list(range(n_keys)), "perm is a bijection"
+    assert (rank[perm] == np.arange(n_keys)).all(), "rank is the inverse of perm"
+    cnt = np.bincount(fact, minlength=n_keys) if fact.size else np.zeros(n_keys, np.int64)
+    assert (L.counts_by_rank == cnt[perm]).all()
+    assert (np.diff(L.counts_by_rank) <= 0).all(), "frequencies non-increasing along perm"
+    ties = np.diff(L.counts_by_rank) == 0
+    assert (np.diff(perm)[ties] > 0).all(), "equal frequencies in ascending key order"
+    assert L.counts_by_rank.sum() == fact.size
+    assert (L.fact_recoded == rank[fact]).all()
+    if price is not None:
+        assert (L.price[L.fact_recoded] == price[fact]).all(), "materialisation through the new layout"
+    if category is not None:
+        assert (L.category[L.fact_recoded] == category[fact]).all()
+
+
+def pin_layout_invariants(orc):
+    for seed in range(6):
+        rng = np.random.default_rng(300 + seed)
+        n = int(rng.integers(1, 2000))
+        f = int(rng.integers(0, 20000))
+        w = rng.zipf(1.5, f) % n if f else np.zeros(0, np.int64)
+        fact = w.astype(np.int32)
+        price = rng.integers(1, 10001, n).astype(np.int32)
+        cat = rng.integers(0, 16, n).astype(np.int8)
+        L = orc.build_layout(fact, n, price, cat)
+        check_layout_invariants(L, fact, n, price, cat)
+
+
+def pin_invariance_all_layouts(orc):
+    """Any bijection used as a layout leaves every answer unchanged (Section 3.2)."""
+    rng = np.random.default_rng(11)
+    n, F = 6, 60
+    fact = rng.integers(0, n, F).astype(np.int32)
+    price = rng.integers(1, 100, n).astype(np.int32)
+    cat = rng.integers(0, 16, n).astype(np.int8)
+    vals = rng.integers(-1000, 1000, F).astype(np.int32)
+    ref = {(lt, by): orc.fk_join_aggregate(fact, price, cat, lt, by) for lt in (4, 16) for by in (False, True)}
+    gs, gc, _ = orc.group_aggregate(fact, vals, n)
+    for p in itertools.permutations(range(n)):
+        perm = np.array(p, dtype=np.int32)
+        rank = np.empty(n, np.int32)
+        rank[perm] = np.arange(n, dtype=np.int32)
+        fr = orc.recode(fact, rank)
+        pp = orc.permute_dim(price, perm)
+        cp = orc.permute_dim(cat, perm)
+        for (lt, by), (s, c) in ref.items():
+            s2, c2 = orc.fk_join_aggregate(fr, pp, cp, lt, by)
+            assert (s == s2).all() and (c == c2).all()
+        s2, c2, _ = orc.group_aggregate(fr, vals, n)
+        # un-permute: group of rank r is key perm[r]
+        us = np.empty_like(s2)
+        uc = np.empty_like(c2)
+        us[perm] = s2
+        uc[perm] = c2
+        assert (us == gs).all() and (uc == gc).all()
+
+
+def pin_stale_layout(orc):
+    """A layout built on one fact column still gives exact answers on another (Section 3.1)."""
+    rng = np.random.default_rng(21)
+    n = 500
+    a = (rng.zipf(1.2, 5000) % n).astype(np.int32)
+    b = rng.integers(0, n, 7000).astype(np.int32)
+    price = rng.integers(1, 10001, n).astype(np.int32)
+    cat = rng.integers(0, 16, n).astype(np.int8)
+    L = orc.build_layout(a, n, price, cat)
+    bn = orc.recode(b, L.rank)
+    for lt, by in ((4, False), (16, True)):
+        s, c = orc.fk_join_aggregate(b, price, cat, lt, by)
+        s2, c2 = orc.fk_join_aggregate(bn, L.price, L.category, lt, by)
+        assert (s == s2).all() and (c == c2).all()
+
+
+ALL_PINS = [pin_fk_bruteforce, pin_fk_special_cases, pin_group_bruteforce, pin_layout_bruteforce, pin_fig2,
+            pin_layout_invariants, pin_invariance_all_layouts, pin_stale_layout]

@@ -1,0 +1,51 @@
+"""Planted mistakes in a copy of the oracle must each fail at least one pin.
+
+Each mutant is a one-token edit of oracle.c (a dropped term, a flipped sign or
+comparison, a transposed index), compiled on the CPU into a temporary library.
+The real oracle.c is never modified.
+"""
+import os
+
+import pytest
+
+import oracle
+from tests import pins
+
+MUTANTS = {
+    "sort_ascending": ("if (a->cnt != b->cnt) return a->cnt > b->cnt ? -1 : 1;",
+                       "if (a->cnt != b->cnt) return a->cnt < b->cnt ? -1 : 1;"),
+    "tie_descending_key": ("return (a->key > b->key) - (a->key < b->key);",
+                           "return (a->key < b->key) - (a->key > b->key);"),
+    "rank_not_inverse": ("for (int32_t r = 0; r < n_keys; ++r) rank[perm[r]] = r;",
+                         "for (int32_t r = 0; r < n_keys; ++r) rank[r] = perm[r];"),
+    "recode_identity": ("C_new[j] = (k >= 0 && k < n_keys) ? rank[k] : k;", "C_new[j] = k;"),
+    "permute_transposed": ("for (int32_t r = 0; r < n_keys; ++r) out[r] = col[perm[r]];\n}\n\nvoid oracle_permute_i8",
+                           "for (int32_t r = 0; r < n_keys; ++r) out[perm[r]] = col[r];\n}\n\nvoid oracle_permute_i8"),
+    "filter_le": ("if (!(c < cat_lt)) continue;", "if (!(c <= cat_lt)) continue;"),
+    "group_ignored": ("      g = c;\n", "      g = 0;\n"),
+    "count_dropped": ("    sum[g] += (int64_t)price[k];\n    count[g] += 1;", "    sum[g] += (int64_t)price[k];"),
+    "group_sum_wrong_index": ("sum[g] += (int64_t)V[j];", "sum[g] += (int64_t)V[g];"),
+    "invalid_key_joined": ("    if (k < 0 || k >= n_rows) continue;\n", "    if (k < 0) continue;\n"),
+    "counts_off_by_one": ("    cnt[k] += 1;\n", "    cnt[k] += (k == 0) ? 2 : 1;\n"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(oracle.SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    path = tmp_path / f"mut_{name}.c"
+    path.write_text(src.replace(old, new))
+    lib = oracle.compile_source(str(path), str(tmp_path / f"libmut_{name}.so"))
+    caught = []
+    try:
+        oracle.use_library(lib)
+        for pin in pins.ALL_PINS:
+            try:
+                pin(oracle)
+            except (AssertionError, IndexError, ValueError):
+                caught.append(pin.__name__)
+    finally:
+        oracle.use_library(None)
+    assert caught, f"no pin catches mutant {name}"
