@@ -1,0 +1,161 @@
+/*
+ * skew.h - C ABI of libskew.so: the frequency-ordered ("permutation index")
+ * layout of Zhang and Ross, "Exploiting Data Skew for Improved Query
+ * Performance", and the foreign-key join-aggregate and grouped aggregation
+ * that run on it, as hand-written HIP kernels for gfx950 (MI355X).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array argument is a DEVICE pointer on the current HIP device, owned
+ *   by the caller, and must be 4-byte aligned (int8 columns: any alignment).
+ *   The library allocates nothing: scratch space comes from the caller's
+ *   `workspace` (device memory of at least skew_workspace_bytes(...) bytes,
+ *   256-byte aligned).
+ * - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on it
+ *   in order; unless stated otherwise a call returns without waiting.
+ * - Keys and groups are 0-based offsets (Section 2.2: a foreign key is an
+ *   array offset into the dimension table).
+ * - All sums and counts are exact 64-bit integers (no floating point).
+ *   Outputs are overwritten, never accumulated into.
+ * - Arguments are checked on the host before any HIP call; a failed check
+ *   returns SKEW_EINVAL or SKEW_ENOSPACE with no device work enqueued.
+ * - Return value: SKEW_OK or a negative code below; skew_last_error() then
+ *   holds a message.  Calls on distinct streams may run concurrently; calls
+ *   that share a workspace must be ordered by the caller.
+ */
+#ifndef SKEW_H
+#define SKEW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SKEW_OK 0
+#define SKEW_EINVAL (-1)   /* null/misaligned pointer, negative size, bad parameter */
+#define SKEW_ERANGE (-2)   /* a key or group id outside its domain was seen */
+#define SKEW_ENOSPACE (-3) /* workspace smaller than skew_workspace_bytes(...) */
+#define SKEW_EHIP (-4)     /* HIP runtime or launch failure */
+#define SKEW_EDEVICE (-5)  /* no usable gfx950 device */
+
+/* Operation ids for skew_workspace_bytes. */
+#define SKEW_OP_BUILD 1
+#define SKEW_OP_JOIN 2
+#define SKEW_OP_GROUP 3
+
+/* hot_rows / hot_groups special values. */
+#define SKEW_HOT_AUTO (-1)  /* library picks the hot prefix from LDS capacity */
+#define SKEW_HOT_NONE (-2)  /* group_aggregate only: global atomics for every row */
+
+/* Message of the last failed call on this thread ("" if none); valid until the
+ * next call on the same thread. */
+const char *skew_last_error(void);
+
+/* Bytes of workspace the operation needs for n_fact fact rows and n_keys keys
+ * (dimension rows for BUILD/JOIN, groups for GROUP).  Returns 0 for an unknown
+ * op or negative sizes. */
+size_t skew_workspace_bytes(int op, int64_t n_fact, int32_t n_keys);
+
+/*
+ * build_skew_layout - build the permutation index of one fact column and apply
+ * it (Section 3.1, Section 3.2, Fig. 2).
+ *
+ *   fact_keys[n_fact]      int32 keys, each in [0, n_keys).
+ *   n_keys                 dimension rows (>= 1); n_fact in [0, 2^32).
+ *   dim_price[n_keys]      int32 dimension column to copy in the new order, or NULL.
+ *   dim_category[n_keys]   int8 dimension column to copy in the new order, or NULL.
+ *   perm[n_keys]           out: offset form, perm[r] = key with frequency rank r.
+ *   rank[n_keys]           out: rank form (the "remap index"), rank[perm[r]] = r.
+ *   counts_by_rank[n_keys] out (nullable): frequency of perm[r], non-increasing.
+ *   fact_recoded[n_fact]   out (nullable): rank[fact_keys[j]]; may equal fact_keys
+ *                          (recoded in place).
+ *   price_out[n_keys]      out (NULL iff dim_price is NULL): dim_price[perm[r]].
+ *   category_out[n_keys]   out (NULL iff dim_category is NULL): dim_category[perm[r]].
+ *
+ * Order: keys by decreasing frequency; equal frequencies by ascending key, so
+ * the layout is unique (keys that never occur come last).  Steps: key
+ * histogram, stable radix sort of keys by frequency, inversion, dimension
+ * copy, fact recode.  The call waits once, after the histogram: if any key is
+ * outside [0, n_keys) it returns SKEW_ERANGE and writes none of the outputs.
+ * Otherwise the remaining steps are enqueued and the call returns at once.
+ */
+int build_skew_layout(const int32_t *fact_keys, int64_t n_fact, int32_t n_keys, const int32_t *dim_price,
+                      const int8_t *dim_category, int32_t *perm, int32_t *rank, uint32_t *counts_by_rank,
+                      int32_t *fact_recoded, int32_t *price_out, int8_t *category_out, void *workspace,
+                      size_t workspace_bytes, void *stream);
+
+/*
+ * fk_join_aggregate - foreign-key join of a fact column with a dimension table,
+ * filtered and aggregated (Q1/Q2 of Section 1 feeding SUM and COUNT), with
+ * threshold-based processing of the hot prefix (Section 4.2).
+ *
+ *   fact_keys[n_fact]     int32 keys into the dimension (identity layout: the
+ *                         original keys; skew layout: fact_recoded).
+ *   dim_price[n_rows]     int32 price column (same layout as the keys).
+ *   dim_category[n_rows]  int8 category column.
+ *   cat_lt                a fact qualifies when its row's category < cat_lt
+ *                         (signed compare; cat_lt >= 128 means no filter).
+ *   group_by_category     0: one output group; 1: 16 groups, group = category,
+ *                         rows with category outside [0, 16) in no group.
+ *   hot_rows              t: dimension rows [0, t) are copied into LDS once per
+ *                         workgroup and read from there (t is clamped to the
+ *                         LDS capacity); 0 = every row read from global memory
+ *                         (the identity-layout method); SKEW_HOT_AUTO.
+ *   out_sum, out_count    out: int64[1] or int64[16].
+ *   workspace             >= skew_workspace_bytes(SKEW_OP_JOIN, n_fact, n_rows).
+ *
+ * Fact keys outside [0, n_rows) join nothing and set the workspace's error
+ * flag (see skew_query_status).  The answer does not depend on t or on the
+ * layout: the same query over (keys, dimension) and over (recoded keys,
+ * permuted dimension) gives identical outputs.  With SKEW_CHECK=1 in the
+ * environment the call waits and returns SKEW_ERANGE when the flag is set.
+ */
+int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_price,
+                      const int8_t *dim_category, int32_t n_rows, int32_t cat_lt, int32_t group_by_category,
+                      int32_t hot_rows, int64_t *out_sum, int64_t *out_count, void *workspace,
+                      size_t workspace_bytes, void *stream);
+
+/*
+ * group_aggregate - grouped SUM and COUNT (Q3 of Section 1) with hybrid
+ * private/shared aggregation (Section 4.3) and per-lane copies of the hottest
+ * groups (Section 4.2.2).
+ *
+ *   group_keys[n_fact]  int32 group ids in [0, n_groups) (skew layout: ranks).
+ *   values[n_fact]      int32 values.
+ *   n_groups            >= 1.
+ *   hot_groups          t > 0: groups [0, t) are aggregated in per-workgroup LDS
+ *                       bins (clamped to capacity), the rest with global
+ *                       atomics; 0: layout-oblivious LDS hash privatisation
+ *                       (the identity-layout method); SKEW_HOT_NONE: global
+ *                       atomics only; SKEW_HOT_AUTO.
+ *   perm[n_groups]      nullable.  If set, group_keys are ranks and the
+ *                       outputs are returned in original-key order:
+ *                       out[perm[r]] = aggregate of rank r.
+ *   out_sum, out_count  out: int64[n_groups].
+ *   workspace           >= skew_workspace_bytes(SKEW_OP_GROUP, n_fact, n_groups).
+ *
+ * Rows whose key is outside [0, n_groups) are skipped and set the error flag.
+ */
+int group_aggregate(const int32_t *group_keys, const int32_t *values, int64_t n_fact, int32_t n_groups,
+                    int32_t hot_groups, const int32_t *perm, int64_t *out_sum, int64_t *out_count,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * skew_query_status - wait for `stream`, then report whether the last
+ * fk_join_aggregate or group_aggregate that used this workspace saw an
+ * out-of-range key (SKEW_ERANGE) or not (SKEW_OK).
+ */
+int skew_query_status(const void *workspace, size_t workspace_bytes, void *stream);
+
+/* Hot-prefix capacities (rows / groups) the kernels can hold in LDS on the
+ * current device, or a negative code. */
+int32_t skew_max_hot_rows(int32_t group_by_category);
+int32_t skew_max_hot_groups(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKEW_H */

@@ -1,0 +1,52 @@
+// Internal launch interface between the C ABI (skew_api.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace skew {
+
+struct DeviceInfo {
+  int device = -1;
+  int cu_count = 0;
+  size_t lds_per_block = 0;  // bytes of LDS one workgroup may use
+};
+
+// ---- layout build (Section 3.1 / 3.2) ----
+constexpr int kSortTile = 4096;  // elements per radix-sort tile
+inline int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_histogram(const int32_t *keys, int64_t n, int32_t n_keys, uint32_t *counts, int32_t *flag,
+                            const DeviceInfo &dev, hipStream_t s);
+// Stable sort of keys 0..n_keys-1 by (count desc, key asc).  Scratch: 4 arrays
+// of n_keys u32 plus 256 * sort_tiles(n_keys) u32 of digit histograms.
+hipError_t launch_rank_sort(const uint32_t *counts_by_key, int32_t n_keys, int64_t n_fact, int32_t *perm,
+                            uint32_t *counts_by_rank, uint32_t *keys_a, uint32_t *keys_b, int32_t *vals_a,
+                            int32_t *vals_b, uint32_t *digit_hist, hipStream_t s);
+hipError_t launch_inverse(const int32_t *perm, int32_t n, int32_t *rank, hipStream_t s);
+hipError_t launch_permute_dims(const int32_t *perm, int32_t n, const int32_t *price, const int8_t *cat,
+                               int32_t *price_out, int8_t *cat_out, hipStream_t s);
+hipError_t launch_recode(const int32_t *keys, int64_t n, const int32_t *rank, int32_t n_keys, int32_t *out,
+                         const DeviceInfo &dev, hipStream_t s);
+
+// ---- queries (Section 4) ----
+constexpr int kJoinThreads = 1024;
+constexpr int kGroupThreads = 1024;
+constexpr int kGroupCopies = 16;  // hottest ranks kept as per-lane copies (Section 4.2.2)
+size_t join_lds_bytes(int groups, int32_t hot_rows);
+int32_t join_max_hot_rows(int groups, const DeviceInfo &dev);
+size_t group_lds_bytes(int32_t hot_groups);
+int32_t group_max_hot_groups(const DeviceInfo &dev);
+
+hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price, const int8_t *cat, int32_t n_rows,
+                       int32_t cat_lt, int32_t by_cat, int32_t hot_rows, int64_t *out_sum, int64_t *out_cnt,
+                       uint32_t *words, int32_t *flag, const DeviceInfo &dev, hipStream_t s);
+
+enum GroupMode { kGroupRange = 0, kGroupHash = 1, kGroupAtomic = 2 };
+hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact, int32_t n_groups, GroupMode mode,
+                        int32_t hot_groups, const int32_t *perm, int64_t *out_sum, int64_t *out_cnt,
+                        uint64_t *acc_sum, uint64_t *acc_cnt, int32_t *flag, const DeviceInfo &dev, hipStream_t s);
+
+}  // namespace skew

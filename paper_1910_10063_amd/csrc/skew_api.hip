@@ -1,0 +1,277 @@
+// C ABI of libskew.so (declared in include/skew.h): argument checks on the
+// host, workspace carving, device capabilities, and kernel launches on the
+// caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "../../include/skew.h"
+#include "device_common.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int ok() {
+  g_last_error.clear();
+  return SKEW_OK;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(SKEW_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
+bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+size_t round_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool check_enabled() {
+  static const bool on = [] {
+    const char *v = std::getenv("SKEW_CHECK");
+    return v && v[0] && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
+
+// Device capabilities, queried once per device.
+constexpr int kMaxDevices = 64;
+std::once_flag g_dev_once[kMaxDevices];
+skew::DeviceInfo g_dev[kMaxDevices];
+int g_dev_status[kMaxDevices];
+
+int device_info(skew::DeviceInfo *out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(SKEW_EDEVICE, "no HIP device: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SKEW_EDEVICE, "device id %d out of range", dev);
+  std::call_once(g_dev_once[dev], [dev] {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      g_dev_status[dev] = SKEW_EDEVICE;
+      return;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+      g_dev_status[dev] = SKEW_EDEVICE;
+      return;
+    }
+    g_dev[dev].device = dev;
+    g_dev[dev].cu_count = prop.multiProcessorCount;
+    g_dev[dev].lds_per_block = prop.sharedMemPerBlock;
+    g_dev_status[dev] = SKEW_OK;
+  });
+  if (g_dev_status[dev] != SKEW_OK)
+    return fail(SKEW_EDEVICE, "device %d is not a usable gfx950 device", dev);
+  *out = g_dev[dev];
+  return SKEW_OK;
+}
+
+// Workspace layouts.  The first 256 bytes always hold the query error flag.
+struct BuildWs {
+  size_t counts, keys_a, keys_b, vals_a, vals_b, hist, total;
+};
+
+BuildWs build_ws(int32_t n_keys) {
+  BuildWs w;
+  const size_t n4 = round_up((size_t)n_keys * 4);
+  w.counts = skew::kFlagBytes;
+  w.keys_a = w.counts + n4;
+  w.keys_b = w.keys_a + n4;
+  w.vals_a = w.keys_b + n4;
+  w.vals_b = w.vals_a + n4;
+  w.hist = w.vals_b + n4;
+  w.total = w.hist + round_up((size_t)256 * 4 * (size_t)skew::sort_tiles(n_keys));
+  return w;
+}
+
+size_t join_ws(int32_t n_rows) { return skew::kFlagBytes + round_up((size_t)n_rows * 4); }
+
+size_t group_ws(int32_t n_groups) { return skew::kFlagBytes + 2 * round_up((size_t)n_groups * 8); }
+
+int read_flag(const void *workspace, hipStream_t s) {
+  int32_t flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, workspace, sizeof flag, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "reading the error flag");
+  return flag ? fail(SKEW_ERANGE, "a key outside its domain was seen") : ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *skew_last_error(void) { return g_last_error.c_str(); }
+
+size_t skew_workspace_bytes(int op, int64_t n_fact, int32_t n_keys) {
+  if (n_fact < 0 || n_keys < 0) return 0;
+  switch (op) {
+    case SKEW_OP_BUILD:
+      return build_ws(n_keys).total;
+    case SKEW_OP_JOIN:
+      return join_ws(n_keys);
+    case SKEW_OP_GROUP:
+      return group_ws(n_keys);
+    default:
+      return 0;
+  }
+}
+
+int build_skew_layout(const int32_t *fact_keys, int64_t n_fact, int32_t n_keys, const int32_t *dim_price,
+                      const int8_t *dim_category, int32_t *perm, int32_t *rank, uint32_t *counts_by_rank,
+                      int32_t *fact_recoded, int32_t *price_out, int8_t *category_out, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+  if (n_fact < 0 || n_fact >= (int64_t)1 << 32) return fail(SKEW_EINVAL, "n_fact must be in [0, 2^32)");
+  if (n_keys < 1) return fail(SKEW_EINVAL, "n_keys must be >= 1");
+  if (n_fact > 0 && !fact_keys) return fail(SKEW_EINVAL, "fact_keys is NULL");
+  if (!perm || !rank) return fail(SKEW_EINVAL, "perm and rank are required");
+  if (!workspace) return fail(SKEW_EINVAL, "workspace is NULL");
+  if ((dim_price == nullptr) != (price_out == nullptr))
+    return fail(SKEW_EINVAL, "dim_price and price_out must both be set or both be NULL");
+  if ((dim_category == nullptr) != (category_out == nullptr))
+    return fail(SKEW_EINVAL, "dim_category and category_out must both be set or both be NULL");
+  if (!aligned4(fact_keys) || !aligned4(perm) || !aligned4(rank) || !aligned4(counts_by_rank) ||
+      !aligned4(fact_recoded) || !aligned4(dim_price) || !aligned4(price_out))
+    return fail(SKEW_EINVAL, "32-bit arrays must be 4-byte aligned");
+  if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
+  const BuildWs w = build_ws(n_keys);
+  if (workspace_bytes < w.total)
+    return fail(SKEW_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, w.total);
+
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  int32_t *flag = (int32_t *)ws;
+  uint32_t *counts = (uint32_t *)(ws + w.counts);
+
+  // 1. key histogram (aggregation Q3), then wait once to validate the keys.
+  hipError_t e = skew::launch_fill_u32((uint32_t *)flag, 1, 0u, s);
+  if (e == hipSuccess) e = skew::launch_fill_u32(counts, n_keys, 0u, s);
+  if (e == hipSuccess) e = skew::launch_histogram(fact_keys, n_fact, n_keys, counts, flag, dev, s);
+  if (e != hipSuccess) return hip_fail(e, "histogram launch");
+  int32_t bad = 0;
+  e = hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "histogram");
+  if (bad) return fail(SKEW_ERANGE, "a fact key lies outside [0, %d)", n_keys);
+
+  // 2. sort keys by frequency, 3. invert, 4. copy the dimension, 5. recode the facts.
+  e = skew::launch_rank_sort(counts, n_keys, n_fact, perm, counts_by_rank, (uint32_t *)(ws + w.keys_a),
+                             (uint32_t *)(ws + w.keys_b), (int32_t *)(ws + w.vals_a), (int32_t *)(ws + w.vals_b),
+                             (uint32_t *)(ws + w.hist), s);
+  if (e == hipSuccess) e = skew::launch_inverse(perm, n_keys, rank, s);
+  if (e == hipSuccess) e = skew::launch_permute_dims(perm, n_keys, dim_price, dim_category, price_out, category_out, s);
+  if (e == hipSuccess && fact_recoded) e = skew::launch_recode(fact_keys, n_fact, rank, n_keys, fact_recoded, dev, s);
+  if (e != hipSuccess) return hip_fail(e, "layout launch");
+  return ok();
+}
+
+int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_price,
+                      const int8_t *dim_category, int32_t n_rows, int32_t cat_lt, int32_t group_by_category,
+                      int32_t hot_rows, int64_t *out_sum, int64_t *out_count, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+  if (n_fact < 0) return fail(SKEW_EINVAL, "n_fact must be >= 0");
+  if (n_rows < 1) return fail(SKEW_EINVAL, "n_rows must be >= 1");
+  if (n_fact > 0 && !fact_keys) return fail(SKEW_EINVAL, "fact_keys is NULL");
+  if (!dim_price || !dim_category) return fail(SKEW_EINVAL, "dimension columns are required");
+  if (!out_sum || !out_count) return fail(SKEW_EINVAL, "outputs are required");
+  if (!workspace) return fail(SKEW_EINVAL, "workspace is NULL");
+  if (group_by_category != 0 && group_by_category != 1) return fail(SKEW_EINVAL, "group_by_category must be 0 or 1");
+  if (hot_rows < SKEW_HOT_AUTO) return fail(SKEW_EINVAL, "hot_rows must be >= 0 or SKEW_HOT_AUTO");
+  if (!aligned4(fact_keys) || !aligned4(dim_price) || !aligned4(out_sum) || !aligned4(out_count))
+    return fail(SKEW_EINVAL, "32/64-bit arrays must be 4-byte aligned");
+  if (((uintptr_t)out_sum & 7u) || ((uintptr_t)out_count & 7u))
+    return fail(SKEW_EINVAL, "outputs must be 8-byte aligned");
+  if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = join_ws(n_rows);
+  if (workspace_bytes < need) return fail(SKEW_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const int groups = group_by_category ? 16 : 1;
+  const int32_t t = hot_rows == SKEW_HOT_AUTO ? skew::join_max_hot_rows(groups, dev) : hot_rows;
+  const hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  const hipError_t e = skew::launch_join(fact_keys, n_fact, dim_price, dim_category, n_rows, cat_lt,
+                                         group_by_category, t, out_sum, out_count,
+                                         (uint32_t *)(ws + skew::kFlagBytes), (int32_t *)ws, dev, s);
+  if (e != hipSuccess) return hip_fail(e, "join launch");
+  if (check_enabled()) return read_flag(workspace, s);
+  return ok();
+}
+
+int group_aggregate(const int32_t *group_keys, const int32_t *values, int64_t n_fact, int32_t n_groups,
+                    int32_t hot_groups, const int32_t *perm, int64_t *out_sum, int64_t *out_count, void *workspace,
+                    size_t workspace_bytes, void *stream) {
+  if (n_fact < 0) return fail(SKEW_EINVAL, "n_fact must be >= 0");
+  if (n_groups < 1) return fail(SKEW_EINVAL, "n_groups must be >= 1");
+  if (n_fact > 0 && (!group_keys || !values)) return fail(SKEW_EINVAL, "group_keys and values are required");
+  if (!out_sum || !out_count) return fail(SKEW_EINVAL, "outputs are required");
+  if (!workspace) return fail(SKEW_EINVAL, "workspace is NULL");
+  if (hot_groups < SKEW_HOT_NONE) return fail(SKEW_EINVAL, "hot_groups must be >= 0, SKEW_HOT_AUTO or SKEW_HOT_NONE");
+  if (!aligned4(group_keys) || !aligned4(values) || !aligned4(perm))
+    return fail(SKEW_EINVAL, "32-bit arrays must be 4-byte aligned");
+  if (((uintptr_t)out_sum & 7u) || ((uintptr_t)out_count & 7u))
+    return fail(SKEW_EINVAL, "outputs must be 8-byte aligned");
+  if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = group_ws(n_groups);
+  if (workspace_bytes < need) return fail(SKEW_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  skew::GroupMode mode = skew::kGroupRange;
+  int32_t t = hot_groups;
+  if (hot_groups == SKEW_HOT_NONE) {
+    mode = skew::kGroupAtomic;
+    t = 0;
+  } else if (hot_groups == 0) {
+    mode = skew::kGroupHash;
+    if (dev.lds_per_block < 128 * 1024) return fail(SKEW_EDEVICE, "hash privatisation needs 128 KB of LDS");
+  } else if (hot_groups == SKEW_HOT_AUTO) {
+    t = skew::group_max_hot_groups(dev);
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  const size_t acc = round_up((size_t)n_groups * 8);
+  const hipError_t e = skew::launch_group(group_keys, values, n_fact, n_groups, mode, t, perm, out_sum, out_count,
+                                          (uint64_t *)(ws + skew::kFlagBytes),
+                                          (uint64_t *)(ws + skew::kFlagBytes + acc), (int32_t *)ws, dev, s);
+  if (e != hipSuccess) return hip_fail(e, "group launch");
+  if (check_enabled()) return read_flag(workspace, s);
+  return ok();
+}
+
+int skew_query_status(const void *workspace, size_t workspace_bytes, void *stream) {
+  if (!workspace || workspace_bytes < skew::kFlagBytes) return fail(SKEW_EINVAL, "workspace is NULL or too small");
+  return read_flag(workspace, (hipStream_t)stream);
+}
+
+int32_t skew_max_hot_rows(int32_t group_by_category) {
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  return skew::join_max_hot_rows(group_by_category ? 16 : 1, dev);
+}
+
+int32_t skew_max_hot_groups(void) {
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  return skew::group_max_hot_groups(dev);
+}
+
+}  // extern "C"

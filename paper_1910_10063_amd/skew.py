@@ -1,0 +1,217 @@
+"""Python binding of libskew.so (include/skew.h): argument marshalling only.
+
+Every step runs in the HIP kernels behind the C ABI; this module only checks
+tensor dtypes/devices, allocates outputs and workspace with torch, and passes
+raw device pointers and the current torch stream.  There is no fallback: if
+the library is not built or no gfx950 device is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libskew.so")
+
+SKEW_OK = 0
+SKEW_EINVAL = -1
+SKEW_ERANGE = -2
+SKEW_ENOSPACE = -3
+SKEW_EHIP = -4
+SKEW_EDEVICE = -5
+
+SKEW_OP_BUILD = 1
+SKEW_OP_JOIN = 2
+SKEW_OP_GROUP = 3
+
+SKEW_HOT_AUTO = -1
+SKEW_HOT_NONE = -2
+
+EXPORTED = ("skew_last_error", "skew_workspace_bytes", "build_skew_layout", "fk_join_aggregate", "group_aggregate",
+            "skew_query_status", "skew_max_hot_rows", "skew_max_hot_groups")
+
+
+class SkewError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"skew error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libskew.so (after torch, so both use torch's HIP runtime) and declare signatures."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_1910_10063_amd.build_ext`")
+    lib = ctypes.CDLL(path)
+    P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    lib.skew_last_error.argtypes = []
+    lib.skew_last_error.restype = ctypes.c_char_p
+    lib.skew_workspace_bytes.argtypes = [ctypes.c_int, I64, I32]
+    lib.skew_workspace_bytes.restype = SZ
+    lib.build_skew_layout.argtypes = [P, I64, I32, P, P, P, P, P, P, P, P, P, SZ, P]
+    lib.build_skew_layout.restype = ctypes.c_int
+    lib.fk_join_aggregate.argtypes = [P, I64, P, P, I32, I32, I32, I32, P, P, P, SZ, P]
+    lib.fk_join_aggregate.restype = ctypes.c_int
+    lib.group_aggregate.argtypes = [P, P, I64, I32, I32, P, P, P, P, SZ, P]
+    lib.group_aggregate.restype = ctypes.c_int
+    lib.skew_query_status.argtypes = [P, SZ, P]
+    lib.skew_query_status.restype = ctypes.c_int
+    lib.skew_max_hot_rows.argtypes = [I32]
+    lib.skew_max_hot_rows.restype = I32
+    lib.skew_max_hot_groups.argtypes = []
+    lib.skew_max_hot_groups.restype = I32
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def hip_runtimes_loaded() -> list[str]:
+    """Paths of the HIP runtime libraries mapped into this process."""
+    maps = open("/proc/self/maps").read().splitlines()
+    return sorted({m.split()[-1] for m in maps if "libamdhip64" in m})
+
+
+def _check(rc: int):
+    if rc != SKEW_OK:
+        raise SkewError(rc, _lib.skew_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need(t, dtype, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def workspace_bytes(op: int, n_fact: int, n_keys: int) -> int:
+    return int(load_library().skew_workspace_bytes(op, n_fact, n_keys))
+
+
+def workspace(op: int, n_fact: int, n_keys: int, device) -> torch.Tensor:
+    """A workspace tensor for `op` (uint8, 256-byte aligned by torch's allocator)."""
+    nb = workspace_bytes(op, n_fact, n_keys)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+@dataclass
+class Layout:
+    """Device tensors of one permutation index and the data it rewrote."""
+
+    perm: torch.Tensor  # int32[n_keys]: key of rank r
+    rank: torch.Tensor  # int32[n_keys]: rank of key k
+    counts_by_rank: torch.Tensor  # uint32 values in an int32 tensor (frequencies < 2^31 here) [n_keys]
+    fact_recoded: torch.Tensor | None
+    price: torch.Tensor | None
+    category: torch.Tensor | None
+
+
+def build_skew_layout(fact_keys: torch.Tensor, n_keys: int, price: torch.Tensor | None = None,
+                      category: torch.Tensor | None = None, in_place: bool = False, recode: bool = True,
+                      ws: torch.Tensor | None = None) -> Layout:
+    lib = load_library()
+    _need(fact_keys, torch.int32, "fact_keys")
+    dev = fact_keys.device
+    if price is not None:
+        _need(price, torch.int32, "price")
+    if category is not None:
+        _need(category, torch.int8, "category")
+    perm = torch.empty(n_keys, dtype=torch.int32, device=dev)
+    rank = torch.empty(n_keys, dtype=torch.int32, device=dev)
+    cbr = torch.empty(n_keys, dtype=torch.int32, device=dev)
+    fr = (fact_keys if in_place else torch.empty_like(fact_keys)) if recode else None
+    po = torch.empty(n_keys, dtype=torch.int32, device=dev) if price is not None else None
+    co = torch.empty(n_keys, dtype=torch.int8, device=dev) if category is not None else None
+    if ws is None:
+        ws = workspace(SKEW_OP_BUILD, fact_keys.numel(), n_keys, dev)
+    _check(lib.build_skew_layout(_ptr(fact_keys), fact_keys.numel(), n_keys, _ptr(price), _ptr(category),
+                                 _ptr(perm), _ptr(rank), _ptr(cbr), _ptr(fr), _ptr(po), _ptr(co), _ptr(ws),
+                                 ws.numel(), _stream(dev)))
+    return Layout(perm, rank, cbr, fr, po, co)
+
+
+def fk_join_aggregate(fact_keys: torch.Tensor, price: torch.Tensor, category: torch.Tensor, cat_lt: int,
+                      group_by_category: bool, hot_rows: int = SKEW_HOT_AUTO, ws: torch.Tensor | None = None,
+                      out: tuple[torch.Tensor, torch.Tensor] | None = None):
+    """Returns (sum, count): int64 tensors of 1 or 16 groups."""
+    lib = load_library()
+    _need(fact_keys, torch.int32, "fact_keys")
+    _need(price, torch.int32, "price")
+    _need(category, torch.int8, "category")
+    if price.numel() != category.numel():
+        raise ValueError("price and category must have the same length")
+    dev = fact_keys.device
+    g = 16 if group_by_category else 1
+    if out is None:
+        out = (torch.empty(g, dtype=torch.int64, device=dev), torch.empty(g, dtype=torch.int64, device=dev))
+    if ws is None:
+        ws = workspace(SKEW_OP_JOIN, fact_keys.numel(), price.numel(), dev)
+    _check(lib.fk_join_aggregate(_ptr(fact_keys), fact_keys.numel(), _ptr(price), _ptr(category), price.numel(),
+                                 int(cat_lt), 1 if group_by_category else 0, int(hot_rows), _ptr(out[0]),
+                                 _ptr(out[1]), _ptr(ws), ws.numel(), _stream(dev)))
+    return out
+
+
+def group_aggregate(group_keys: torch.Tensor, values: torch.Tensor, n_groups: int,
+                    hot_groups: int = SKEW_HOT_AUTO, perm: torch.Tensor | None = None,
+                    ws: torch.Tensor | None = None, out: tuple[torch.Tensor, torch.Tensor] | None = None):
+    """Returns (sum, count): int64 tensors of n_groups entries, in original key order."""
+    lib = load_library()
+    _need(group_keys, torch.int32, "group_keys")
+    _need(values, torch.int32, "values")
+    if group_keys.numel() != values.numel():
+        raise ValueError("group_keys and values must have the same length")
+    if perm is not None:
+        _need(perm, torch.int32, "perm")
+    dev = group_keys.device
+    if out is None:
+        out = (torch.empty(n_groups, dtype=torch.int64, device=dev),
+               torch.empty(n_groups, dtype=torch.int64, device=dev))
+    if ws is None:
+        ws = workspace(SKEW_OP_GROUP, group_keys.numel(), n_groups, dev)
+    _check(lib.group_aggregate(_ptr(group_keys), _ptr(values), group_keys.numel(), n_groups, int(hot_groups),
+                               _ptr(perm), _ptr(out[0]), _ptr(out[1]), _ptr(ws), ws.numel(), _stream(dev)))
+    return out
+
+
+def query_status(ws: torch.Tensor) -> int:
+    """SKEW_OK, or raises SkewError(SKEW_ERANGE) if the last query on ws saw an out-of-range key."""
+    lib = load_library()
+    rc = lib.skew_query_status(_ptr(ws), ws.numel(), _stream(ws.device))
+    _check(rc)
+    return rc
+
+
+def max_hot_rows(group_by_category: bool) -> int:
+    v = load_library().skew_max_hot_rows(1 if group_by_category else 0)
+    if v < 0:
+        _check(v)
+    return int(v)
+
+
+def max_hot_groups() -> int:
+    v = load_library().skew_max_hot_groups()
+    if v < 0:
+        _check(v)
+    return int(v)

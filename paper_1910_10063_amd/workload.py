@@ -179,3 +179,51 @@ def device_uniform_i32(seed: int, lo: int, hi: int, n: int, device, out=None, st
     if rc != 0:
         raise RuntimeError(f"skewgen_uniform_i32 failed ({rc})")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Whole workloads (host or device resident)
+# ---------------------------------------------------------------------------
+def host_join_inputs(k: int, n_rows: int, n_fact: int, s: float):
+    """Dimension (price, category) and Zipf fact keys of workload k, as numpy arrays."""
+    cdf = zipf_cdf(n_rows, s)
+    pi = permutation(perm_seed(k), n_rows)
+    fact = fact_keys(fact_seed(k), cdf, pi, n_fact)
+    price, cat = dimension(k, n_rows)
+    return dict(fact=fact, price=price, category=cat, pi=pi, cdf=cdf)
+
+
+def device_join_inputs(k: int, n_rows: int, n_fact: int, s: float, device="cuda"):
+    """Same columns as host_join_inputs, with the fact column generated on the device."""
+    import torch
+
+    cdf = zipf_cdf(n_rows, s)
+    pi = permutation(perm_seed(k), n_rows)
+    price, cat = dimension(k, n_rows)
+    cdf_d = torch.from_numpy(cdf).to(device)
+    pi_d = torch.from_numpy(pi).to(device)
+    fact = device_fact_keys(fact_seed(k), cdf_d, pi_d, n_fact)
+    del cdf_d
+    return dict(fact=fact, price=torch.from_numpy(price).to(device), category=torch.from_numpy(cat).to(device),
+                pi=pi, cdf=cdf)
+
+
+def host_group_inputs(k: int, n_groups: int, n_fact: int, s: float, vmax: int = 1000):
+    cdf = zipf_cdf(n_groups, s)
+    pi = permutation(perm_seed(k), n_groups)
+    keys = fact_keys(fact_seed(k), cdf, pi, n_fact)
+    vals = uniform_int(value_seed(k), 0, vmax, n_fact).astype(np.int32)
+    return dict(keys=keys, vals=vals, pi=pi, cdf=cdf)
+
+
+def device_group_inputs(k: int, n_groups: int, n_fact: int, s: float, vmax: int = 1000, device="cuda"):
+    import torch
+
+    cdf = zipf_cdf(n_groups, s)
+    pi = permutation(perm_seed(k), n_groups)
+    cdf_d = torch.from_numpy(cdf).to(device)
+    pi_d = torch.from_numpy(pi).to(device)
+    keys = device_fact_keys(fact_seed(k), cdf_d, pi_d, n_fact)
+    del cdf_d
+    vals = device_uniform_i32(value_seed(k), 0, vmax, n_fact, device)
+    return dict(keys=keys, vals=vals, pi=pi, cdf=cdf)

@@ -1,0 +1,136 @@
+"""The C ABI of libskew.so on the host: symbols and argument checks (no GPU needed).
+
+Fake device addresses are passed where the call must fail before touching
+the device; every case here returns before the first HIP call.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1910_10063_amd import skew
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "skew.h")
+
+A = ctypes.c_void_p(0x10000)  # aligned fake device address
+A2 = ctypes.c_void_p(0x20000)
+MIS = ctypes.c_void_p(0x10002)  # not 4-byte aligned
+WS = ctypes.c_void_p(0x40000)  # 256-byte aligned
+WS_MIS = ctypes.c_void_p(0x40010)
+NULL = None
+S = ctypes.c_void_p(0)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return skew.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert set(names) == set(skew.EXPORTED), names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_workspace_sizes(lib):
+    assert lib.skew_workspace_bytes(skew.SKEW_OP_JOIN, 10, 1000) >= 256 + 4000
+    assert lib.skew_workspace_bytes(skew.SKEW_OP_GROUP, 10, 1000) >= 256 + 16000
+    b = lib.skew_workspace_bytes(skew.SKEW_OP_BUILD, 10, 100_000)
+    assert b >= 256 + 4 * 5 * 100_000
+    assert lib.skew_workspace_bytes(99, 10, 10) == 0
+    assert lib.skew_workspace_bytes(skew.SKEW_OP_JOIN, -1, 10) == 0
+    assert all(lib.skew_workspace_bytes(op, 0, 7) % 256 == 0 for op in (1, 2, 3))
+
+
+def _build(lib, **kw):
+    a = dict(fact=A, n_fact=10, n_keys=5, price=NULL, cat=NULL, perm=A, rank=A2, cbr=NULL, fr=NULL, po=NULL,
+             co=NULL, ws=WS, wsb=1 << 20, stream=S)
+    a.update(kw)
+    return lib.build_skew_layout(a["fact"], a["n_fact"], a["n_keys"], a["price"], a["cat"], a["perm"], a["rank"],
+                                 a["cbr"], a["fr"], a["po"], a["co"], a["ws"], a["wsb"], a["stream"])
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_fact=-1), skew.SKEW_EINVAL),
+    (dict(n_fact=1 << 32), skew.SKEW_EINVAL),
+    (dict(n_keys=0), skew.SKEW_EINVAL),
+    (dict(fact=NULL), skew.SKEW_EINVAL),
+    (dict(perm=NULL), skew.SKEW_EINVAL),
+    (dict(rank=NULL), skew.SKEW_EINVAL),
+    (dict(ws=NULL), skew.SKEW_EINVAL),
+    (dict(price=A), skew.SKEW_EINVAL),            # price without price_out
+    (dict(co=A), skew.SKEW_EINVAL),               # category_out without category
+    (dict(fact=MIS), skew.SKEW_EINVAL),
+    (dict(ws=WS_MIS), skew.SKEW_EINVAL),
+    (dict(wsb=100), skew.SKEW_ENOSPACE),
+])
+def test_build_rejects(lib, kw, code):
+    assert _build(lib, **kw) == code
+    assert lib.skew_last_error().decode()
+
+
+def _join(lib, **kw):
+    a = dict(fact=A, n_fact=10, price=A, cat=A2, n_rows=5, cat_lt=4, by=0, hot=0, s=A, c=A2, ws=WS, wsb=1 << 20)
+    a.update(kw)
+    return lib.fk_join_aggregate(a["fact"], a["n_fact"], a["price"], a["cat"], a["n_rows"], a["cat_lt"], a["by"],
+                                 a["hot"], a["s"], a["c"], a["ws"], a["wsb"], S)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_fact=-5), skew.SKEW_EINVAL),
+    (dict(n_rows=0), skew.SKEW_EINVAL),
+    (dict(fact=NULL), skew.SKEW_EINVAL),
+    (dict(price=NULL), skew.SKEW_EINVAL),
+    (dict(cat=NULL), skew.SKEW_EINVAL),
+    (dict(s=NULL), skew.SKEW_EINVAL),
+    (dict(by=2), skew.SKEW_EINVAL),
+    (dict(hot=-3), skew.SKEW_EINVAL),
+    (dict(s=ctypes.c_void_p(0x10004)), skew.SKEW_EINVAL),  # int64 output not 8-byte aligned
+    (dict(ws=NULL), skew.SKEW_EINVAL),
+    (dict(wsb=255), skew.SKEW_ENOSPACE),
+])
+def test_join_rejects(lib, kw, code):
+    assert _join(lib, **kw) == code
+
+
+def _group(lib, **kw):
+    a = dict(keys=A, vals=A2, n=10, m=5, hot=0, perm=NULL, s=A, c=A2, ws=WS, wsb=1 << 20)
+    a.update(kw)
+    return lib.group_aggregate(a["keys"], a["vals"], a["n"], a["m"], a["hot"], a["perm"], a["s"], a["c"], a["ws"],
+                               a["wsb"], S)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=-1), skew.SKEW_EINVAL),
+    (dict(m=0), skew.SKEW_EINVAL),
+    (dict(keys=NULL), skew.SKEW_EINVAL),
+    (dict(vals=NULL), skew.SKEW_EINVAL),
+    (dict(hot=-3), skew.SKEW_EINVAL),
+    (dict(perm=MIS), skew.SKEW_EINVAL),
+    (dict(c=NULL), skew.SKEW_EINVAL),
+    (dict(wsb=300), skew.SKEW_ENOSPACE),
+])
+def test_group_rejects(lib, kw, code):
+    assert _group(lib, **kw) == code
+
+
+def test_status_rejects_null(lib):
+    assert lib.skew_query_status(NULL, 0, S) == skew.SKEW_EINVAL
+
+
+def test_valid_call_without_gpu_reports_edevice(lib):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert _join(lib) == skew.SKEW_EDEVICE
+    assert "device" in lib.skew_last_error().decode()
