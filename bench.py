@@ -1,0 +1,301 @@
+#!/usr/bin/env python3
+"""Benchmark of the skew-layout FK join-aggregate on one MI355X.
+
+Workload (defaults): a 1e7-row dimension table (price U[1,10000] int32,
+category U[0,15] int8) and 1e9 int32 fact keys drawn Zipf s=1.0 over ranks and
+mapped to keys by a seeded permutation; query SUM(price), COUNT(*) grouped by
+category (16 groups), int64 results.  All inputs are synthetic and generated
+on the device from fixed seeds.
+
+One timed step is one query over the whole fact column on the skew layout
+(recoded keys + permuted dimension): the per-query dimension pack and the
+join-aggregate kernel, inputs already resident in HBM.  The layout build is
+timed on its own, as the paper reports index-build cost apart from queries
+(Section 5.1).  Beside the headline number the JSON line carries the
+identity-layout baseline, the build time, the Zipf and hot-prefix sweeps, the
+grouped aggregation on a 1e6-group / 5e8-row workload, the roofline of the
+dominant kernel and the CPU oracle timed on the host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "fact tuples/s and % of HBM roofline, skew layout vs identity layout (bit-exact)"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "join_kernel_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1910_10063_amd", "csrc", f)
+                  for f in ("query_kernels.hip", "device_common.h", "kernels.h")]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def timed(fn, steps, warmup, stream):
+    """Run fn warmup times, then time `steps` runs with HIP events on `stream`."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps  # ms per run
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-rows", type=int, default=10_000_000)
+    ap.add_argument("--n-fact", type=int, default=1_000_000_000)
+    ap.add_argument("--zipf", type=float, default=1.0)
+    ap.add_argument("--hot-rows", type=int, default=-1, help="hot prefix in LDS (-1: library default)")
+    ap.add_argument("--cpu-rows", type=int, default=1_000_000_000, help="fact rows the CPU oracle is timed on")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extras", action="store_true", help="headline query only (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device copy of 1 GiB (reference for profiler byte counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the skew-layout path runs on a single MI355X; "
+              "a multi-GPU run would shard the fact column and is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1910_10063_amd import skew
+    from paper_1910_10063_amd import workload as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    N, F, S = args.n_rows, args.n_fact, args.zipf
+    K, WU = args.steps, args.warmup
+    k = 2  # seeds of the 16-group join workload
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    log(f"generating N={N} F={F} s={S}")
+    inp = W.device_join_inputs(k, N, F, S, dev)
+    C, price, cat = inp["fact"], inp["price"], inp["category"]
+
+    # ---- layout build (Section 3.1): histogram, rank sort, inverse, dimension copy, recode
+    bws = skew.workspace(skew.SKEW_OP_BUILD, F, N, dev)
+    Cp = torch.empty_like(C)
+    perm = torch.empty(N, dtype=torch.int32, device=dev)
+    rank = torch.empty(N, dtype=torch.int32, device=dev)
+    cbr = torch.empty(N, dtype=torch.int32, device=dev)
+    pp = torch.empty(N, dtype=torch.int32, device=dev)
+    cp = torch.empty(N, dtype=torch.int8, device=dev)
+    lib = skew.load_library()
+
+    def build():
+        rc = lib.build_skew_layout(C.data_ptr(), F, N, price.data_ptr(), cat.data_ptr(), perm.data_ptr(),
+                                   rank.data_ptr(), cbr.data_ptr(), Cp.data_ptr(), pp.data_ptr(), cp.data_ptr(),
+                                   bws.data_ptr(), bws.numel(), stream.cuda_stream)
+        if rc:
+            raise skew.SkewError(rc, lib.skew_last_error().decode())
+
+    log("layout build")
+    build_ms = timed(build, 3, 1, stream)
+
+    # ---- queries
+    jws = skew.workspace(skew.SKEW_OP_JOIN, F, N, dev)
+    out_s = torch.empty(16, dtype=torch.int64, device=dev)
+    out_c = torch.empty(16, dtype=torch.int64, device=dev)
+    empty = torch.empty(0, dtype=torch.int32, device=dev)
+    t_hot = args.hot_rows
+
+    def query(keys, pr, ca, t):
+        return lambda: skew.fk_join_aggregate(keys, pr, ca, 16, True, hot_rows=t, ws=jws, out=(out_s, out_c))
+
+    log("skew-layout query (timed steps)")
+    ms_skew = timed(query(Cp, pp, cp, t_hot), K, WU, stream)
+    skew_res = (out_s.cpu().numpy().copy(), out_c.cpu().numpy().copy())
+    log("identity-layout query")
+    ms_ident = timed(query(C, price, cat, 0), K, WU, stream)
+    ident_res = (out_s.cpu().numpy().copy(), out_c.cpu().numpy().copy())
+    ms_pack = timed(query(empty, pp, cp, t_hot), K, WU, stream)  # dimension pack only (empty fact column)
+    ms_join_kernel = max(ms_skew - ms_pack, 1e-6)
+    ms_join_kernel_ident = max(ms_ident - ms_pack, 1e-6)
+    agree = bool((skew_res[0] == ident_res[0]).all() and (skew_res[1] == ident_res[1]).all())
+
+    # roofline of the dominant kernel (join-aggregate): algorithmic bytes = 4 B per fact key
+    # plus 4 B per packed dimension word read once
+    alg_bytes = 4.0 * F + 4.0 * N
+    achieved = alg_bytes / (ms_join_kernel * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("source_sha") == kernel_source_sha() and tr.get("n_fact") == F and tr.get("n_rows") == N \
+                and tr.get("zipf_s") == S:
+            traffic = tr.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": "join_kernel<16>", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": round(ms_join_kernel, 4)}
+
+    result = {
+        "metric": METRIC,
+        "value": F / (ms_skew * 1e-3),
+        "unit": "fact tuples/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": WU,
+        "ms_per_step": ms_skew,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic (seeded Zipf fact keys and uniform dimension columns, generated on the device)",
+        "config": {"workload": f"fk-join-aggregate: {N:.0e}-row dimension, {F:.0e} Zipf(s={S}) int32 fact keys, "
+                               "SUM(price), COUNT(*) GROUP BY category (16 groups), skew layout",
+                   "n_rows": N, "n_fact": F, "zipf_s": S, "groups": 16, "hot_rows": t_hot,
+                   "hot_rows_used": min(skew.max_hot_rows(True), N) if t_hot < 0 else min(t_hot, N),
+                   "seeds": {"fact": W.fact_seed(k), "perm": W.perm_seed(k), "price": W.price_seed(k),
+                             "category": W.category_seed(k)}},
+        "roofline": roofline,
+        "identity": {"value": F / (ms_ident * 1e-3), "ms_per_step": ms_ident,
+                     "kernel_gbs": round(alg_bytes / (ms_join_kernel_ident * 1e-3) / 1e9, 1)},
+        "speedup_vs_identity": ms_ident / ms_skew,
+        "pack_ms": ms_pack,
+        "build": {"ms": build_ms, "fact_tuples_per_s": F / (build_ms * 1e-3)},
+        "layouts_agree": agree,
+    }
+
+    if not args.no_extras:
+        # hot-prefix sweep (rows above the LDS capacity are served from L2: same as the capacity)
+        cap = skew.max_hot_rows(True)
+        sweep_t = []
+        for t in (0, 4096, 8192, 16384, 32768, cap):
+            ms = timed(query(Cp, pp, cp, t), max(K // 2, 3), 1, stream)
+            sweep_t.append({"hot_rows": t, "ms": round(ms, 4), "tuples_per_s": F / (ms * 1e-3)})
+        result["hot_prefix_sweep"] = sweep_t
+        # Zipf sweep: each exponent gets its own fact column and layout
+        sweep_s = []
+        for s in (0.0, 0.5, 1.0, 1.5):
+            log(f"zipf sweep s={s}")
+            d = W.device_join_inputs(k, N, F, s, dev)
+            L = skew.build_skew_layout(d["fact"], N, d["price"], d["category"], in_place=False, ws=bws)
+            ms_i = timed(lambda: skew.fk_join_aggregate(d["fact"], d["price"], d["category"], 16, True, hot_rows=0,
+                                                        ws=jws, out=(out_s, out_c)), max(K // 2, 3), 1, stream)
+            ri = out_s.cpu().numpy().copy()
+            ms_s = timed(lambda: skew.fk_join_aggregate(L.fact_recoded, L.price, L.category, 16, True,
+                                                        hot_rows=t_hot, ws=jws, out=(out_s, out_c)),
+                         max(K // 2, 3), 1, stream)
+            rs = out_s.cpu().numpy().copy()
+            sweep_s.append({"zipf_s": s, "identity_tuples_per_s": F / (ms_i * 1e-3),
+                            "skew_tuples_per_s": F / (ms_s * 1e-3), "speedup": ms_i / ms_s,
+                            "layouts_agree": bool((ri == rs).all())})
+            del d, L
+            torch.cuda.empty_cache()
+        result["zipf_sweep"] = sweep_s
+        result["group_by"] = bench_group_by(K, WU, dev, stream)
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(C, price, cat, args.cpu_rows, skew_res if args.cpu_rows >= F else None)
+        if "bit_exact_vs_oracle" in result["cpu_baseline"]:
+            result["bit_exact_vs_oracle"] = result["cpu_baseline"].pop("bit_exact_vs_oracle")
+    print(json.dumps(result), flush=True)
+
+
+def bench_group_by(K, WU, dev, stream):
+    """Grouped SUM/COUNT over 5e8 rows of Zipf(1.1) keys in 1e6 groups, values U[0,1000]."""
+    import torch
+
+    from paper_1910_10063_amd import skew
+    from paper_1910_10063_amd import workload as W
+
+    M, F, s = 1_000_000, 500_000_000, 1.1
+    log(f"group-by M={M} F={F} s={s}")
+    g = W.device_group_inputs(3, M, F, s, device=dev)
+    G, V = g["keys"], g["vals"]
+    bws = skew.workspace(skew.SKEW_OP_BUILD, F, M, dev)
+    t0 = time.time()
+    L = skew.build_skew_layout(G, M, ws=bws)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    gws = skew.workspace(skew.SKEW_OP_GROUP, F, M, dev)
+    out = (torch.empty(M, dtype=torch.int64, device=dev), torch.empty(M, dtype=torch.int64, device=dev))
+    res = {}
+    for name, keys, t, perm in (("skew", L.fact_recoded, skew.SKEW_HOT_AUTO, L.perm),
+                                ("identity_hash", G, 0, None),
+                                ("identity_atomic", G, skew.SKEW_HOT_NONE, None)):
+        steps = K if name != "identity_atomic" else max(K // 4, 2)
+        ms = timed(lambda: skew.group_aggregate(keys, V, M, hot_groups=t, perm=perm, ws=gws, out=out), steps,
+                   1, stream)
+        res[name] = {"ms": ms, "tuples_per_s": F / (ms * 1e-3),
+                     "sum_digest": hashlib.sha256(out[0].cpu().numpy().tobytes() +
+                                                  out[1].cpu().numpy().tobytes()).hexdigest()[:16]}
+    alg = 8.0 * F + 16.0 * M
+    ms = res["skew"]["ms"]
+    return {"workload": f"group-aggregate: {M:.0e} groups, {F:.0e} rows, Zipf(s={s}) keys, values U[0,1000]",
+            "skew": res["skew"], "identity_hash": res["identity_hash"], "identity_atomic": res["identity_atomic"],
+            "speedup_vs_identity_hash": res["identity_hash"]["ms"] / ms,
+            "roofline_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "build_s_incl_sync": build_s,
+            "layouts_agree": len({r["sum_digest"] for r in res.values()}) == 1}
+
+
+def cpu_baseline(C, price, cat, rows, gpu_res):
+    """The CPU oracle, as it stands, on the first `rows` fact rows of the identity layout (one thread)."""
+    import numpy as np
+
+    import oracle
+
+    n = min(rows, C.numel())
+    log(f"cpu oracle on {n} rows")
+    Ch = C[:n].cpu().numpy()
+    ph = price.cpu().numpy()
+    ch = cat.cpu().numpy()
+    t = time.perf_counter()
+    s, c = oracle.fk_join_aggregate(Ch, ph, ch, 16, True)
+    dt = time.perf_counter() - t
+    out = {"value": n / dt, "unit": "fact tuples/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {n} of {C.numel()} fact rows, identity layout, same query; {dt:.2f} s on 1 thread",
+           "cpu_model": _cpu_model()}
+    if gpu_res is not None:
+        out["bit_exact_vs_oracle"] = bool((s == gpu_res[0]).all() and (c == gpu_res[1]).all())
+    return out
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

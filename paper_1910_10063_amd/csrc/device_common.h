@@ -22,11 +22,6 @@ __device__ __forceinline__ int32_t load_stream1(const int32_t *p) { return __bui
 
 __device__ __forceinline__ void store_stream4(i32x4 *p, i32x4 v) { __builtin_nontemporal_store(v, p); }
 
-__device__ __forceinline__ void raise_flag(int32_t *flag) {
-  // Plain vector store: any writer sets it to 1.
-  *(volatile int32_t *)flag = 1;
-}
-
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);

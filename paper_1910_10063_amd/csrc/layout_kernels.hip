@@ -38,9 +38,9 @@ struct HistTable {
 };
 
 __device__ __forceinline__ void hist_count(const HistTable &t, int32_t k, int32_t n_keys, uint32_t *counts,
-                                           int32_t *flag) {
+                                           bool &bad) {
   if ((uint32_t)k >= (uint32_t)n_keys) {
-    raise_flag(flag);
+    bad = true;
     return;
   }
   const uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - kHistSlotBits);
@@ -71,12 +71,13 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(const int32_t *
   }
   __syncthreads();
   const HistTable t{slot_key, slot_cnt};
+  bool bad = false;
 
   const Split4 sp = split4(keys, n);
   const int64_t T = (int64_t)gridDim.x * blockDim.x;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid < sp.head) hist_count(t, keys[gid], n_keys, counts, flag);
-  if (gid < n - sp.tail) hist_count(t, keys[sp.tail + gid], n_keys, counts, flag);
+  if (gid < sp.head) hist_count(t, keys[gid], n_keys, counts, bad);
+  if (gid < n - sp.tail) hist_count(t, keys[sp.tail + gid], n_keys, counts, bad);
   const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
   int64_t v = gid;
   for (; v + (kHistUnroll - 1) * T < sp.nvec; v += kHistUnroll * T) {
@@ -85,19 +86,20 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(const int32_t *
     for (int u = 0; u < kHistUnroll; ++u) x[u] = load_stream4(vk + v + u * T);
 #pragma unroll
     for (int u = 0; u < kHistUnroll; ++u) {
-      hist_count(t, x[u].x, n_keys, counts, flag);
-      hist_count(t, x[u].y, n_keys, counts, flag);
-      hist_count(t, x[u].z, n_keys, counts, flag);
-      hist_count(t, x[u].w, n_keys, counts, flag);
+      hist_count(t, x[u].x, n_keys, counts, bad);
+      hist_count(t, x[u].y, n_keys, counts, bad);
+      hist_count(t, x[u].z, n_keys, counts, bad);
+      hist_count(t, x[u].w, n_keys, counts, bad);
     }
   }
   for (; v < sp.nvec; v += T) {
     const i32x4 x = load_stream4(vk + v);
-    hist_count(t, x.x, n_keys, counts, flag);
-    hist_count(t, x.y, n_keys, counts, flag);
-    hist_count(t, x.z, n_keys, counts, flag);
-    hist_count(t, x.w, n_keys, counts, flag);
+    hist_count(t, x.x, n_keys, counts, bad);
+    hist_count(t, x.y, n_keys, counts, bad);
+    hist_count(t, x.z, n_keys, counts, bad);
+    hist_count(t, x.w, n_keys, counts, bad);
   }
+  if (bad) *flag = 1;
   __syncthreads();
   for (int i = threadIdx.x; i < kHistSlots; i += blockDim.x) {
     const int32_t k = slot_key[i];

@@ -12,14 +12,18 @@ namespace {
 // the dimension columns it needs in layout order; here the two columns the
 // query needs (price, category) and its predicate are packed into one 32-bit
 // word per row, so a fact row costs one 4-byte gather:
-//   0                     row does not qualify (or has no group)
-//   0x40000000 | g << 26 | price   qualifies, group g, 0 <= price < 2^26
-//   0x80000000            qualifies but the price does not fit: read the
-//                         columns again (exact for any int32 price)
+//   0x80000000 | (g + 1) << 25 | price   qualifies, group g, 0 <= price < 2^25
+//   0x80000000                           does not qualify (or has no group)
+//   0                                    qualifies, but the price does not fit:
+//                                        the slow path reads the columns again
+// A gather outside [0, n_rows) also reads 0 (buffer range check), so every
+// zero word goes to the slow path, which tells the two cases apart.  Field
+// (w >> 25) & 31 selects an accumulator bin; bin 0 is a sink that is never
+// read back.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kQualifies = 0x40000000u;
-constexpr uint32_t kEscape = 0x80000000u;
-constexpr uint32_t kPriceMask = (1u << 26) - 1u;
+constexpr uint32_t kValid = 0x80000000u;
+constexpr int kGroupShift = 25;
+constexpr uint32_t kPriceMask = (1u << kGroupShift) - 1u;
 
 __device__ __forceinline__ bool row_group(int32_t c, int32_t cat_lt, int32_t by_cat, int32_t *g) {
   if (!(c < cat_lt)) return false;
@@ -45,50 +49,139 @@ __global__ void join_pack_kernel(const int32_t *__restrict__ price, const int8_t
   for (int64_t r = gid; r < n_rows; r += stride) {
     const int32_t p = price[r];
     int32_t g;
-    uint32_t w = 0;
+    uint32_t w = kValid;
     if (row_group(cat[r], cat_lt, by_cat, &g))
-      w = ((uint32_t)p <= kPriceMask) ? (kQualifies | ((uint32_t)g << 26) | (uint32_t)p) : kEscape;
+      w = ((uint32_t)p <= kPriceMask) ? (kValid | ((uint32_t)(g + 1) << kGroupShift) | (uint32_t)p) : 0u;
     words[r] = w;
   }
 }
 
+// Structured buffer load: element `index` of a buffer of 4-byte records.  The
+// hardware range check (index < num_records) returns 0 for any other index,
+// negative keys included, without touching memory.
+typedef int32_t rsrc_t __attribute__((ext_vector_type(4)));
+__device__ uint32_t buffer_load_record(rsrc_t rsrc, int32_t vindex, int32_t voffset, int32_t soffset,
+                                       int32_t aux) __asm("llvm.amdgcn.struct.buffer.load.i32");
+
+__device__ __forceinline__ rsrc_t record_buffer(const void *base, uint32_t num_records) {
+  const uint64_t a = (uint64_t)(uintptr_t)base;
+  rsrc_t r;
+  r.x = (int32_t)(uint32_t)a;
+  r.y = (int32_t)(((uint32_t)(a >> 32) & 0xFFFFu) | (4u << 16));  // stride 4 bytes
+  r.z = (int32_t)num_records;
+  r.w = 0x00020000;  // gfx9 raw 32-bit data format
+  return r;
+}
+
 // Join-aggregate.  One workgroup of 1024 threads per CU; dimension rows
-// [0, t_lds) are copied into LDS once per workgroup.  For GROUPS == 16 every
-// lane owns one 64-bit bin per group in LDS, shared by the 16 waves through
-// LDS atomics (no two lanes of a wave ever hit the same bin); a bin packs
-// count << 44 | sum, exact while a bin sees fewer than 2^18 rows.
-constexpr int kJoinUnroll = 4;
+// [0, t_lds) are copied into LDS once per workgroup (Section 4.2.1: ids below
+// the threshold are the likely cache hits and take their own path).  Every
+// fact key is looked up twice without branching: a clamped LDS read and a
+// buffer gather whose index is pushed out of range for hot keys (so it
+// returns 0 and issues no memory traffic); a select keeps the right one.
+// For GROUPS == 16 every lane owns one 64-bit bin per group in LDS, shared by
+// the 16 waves through LDS atomics (two lanes of a wave never hit the same
+// bin); a bin packs count << 44 | sum, exact while it sees fewer than 2^19
+// rows.  For GROUPS == 1 the sums stay in registers.
+constexpr int kJoinVecs = 4;  // 16-byte key vectors per lane per batch
+constexpr int kJoinBins = 32;  // (w >> 25) & 31
 constexpr int kCountShift = 44;
 constexpr uint64_t kSumMask = (1ull << kCountShift) - 1ull;
 
 template <int GROUPS>
-struct JoinAcc {
-  uint64_t sum = 0;
-  uint32_t cnt = 0;
-  uint64_t *bins = nullptr;
+struct JoinCtx {
+  const uint32_t *hot;  // LDS
+  uint64_t *bins;       // LDS [kJoinBins][64], GROUPS == 16
+  rsrc_t words;
+  uint32_t t, tclamp;
+  uint32_t lane8;
+  // GROUPS == 1
+  uint64_t sum;
+  uint32_t cnt;
+  // slow path
+  const int32_t *price;
+  const int8_t *cat;
+  int32_t cat_lt;
+  uint32_t n_rows;
+  int64_t *out_sum, *out_cnt;
+  bool bad;
 };
 
 template <int GROUPS>
-__device__ __forceinline__ void join_consume(JoinAcc<GROUPS> &acc, uint32_t w, int32_t k, const int32_t *price,
-                                             const int8_t *cat, int32_t cat_lt, int64_t *out_sum,
-                                             int64_t *out_cnt) {
-  if (w & kEscape) {  // rare: price outside [0, 2^26)
-    int32_t g;
-    if (row_group(cat[k], cat_lt, GROUPS == 16, &g)) {
-      global_add_u64(reinterpret_cast<uint64_t *>(&out_sum[g]), (uint64_t)(int64_t)price[k]);
-      global_add_u64(reinterpret_cast<uint64_t *>(&out_cnt[g]), 1ull);
-    }
+__device__ __forceinline__ uint32_t join_fetch(const JoinCtx<GROUPS> &c, uint32_t uk) {
+  const bool h = uk < c.t;
+  const uint32_t wl = c.hot[uk < c.tclamp ? uk : c.tclamp];
+  const uint32_t wg = buffer_load_record(c.words, (int32_t)(h ? 0xFFFFFFFFu : uk), 0, 0, 0);
+  return h ? wl : wg;
+}
+
+template <int GROUPS>
+__device__ __forceinline__ void join_slow(JoinCtx<GROUPS> &c, uint32_t uk) {
+  if (uk >= c.n_rows) {
+    c.bad = true;
     return;
   }
-  if (!(w & kQualifies)) return;
-  const uint32_t p = w & kPriceMask;
-  if (GROUPS == 1) {
-    acc.sum += p;
-    acc.cnt += 1;
-  } else {
-    const uint32_t g = (w >> 26) & 15u;
-    lds_add_u64(&acc.bins[g * kWave + lane_id()], (1ull << kCountShift) | p);
+  int32_t g;
+  if (row_group(c.cat[uk], c.cat_lt, GROUPS == 16, &g)) {
+    global_add_u64(reinterpret_cast<uint64_t *>(&c.out_sum[g]), (uint64_t)(int64_t)c.price[uk]);
+    global_add_u64(reinterpret_cast<uint64_t *>(&c.out_cnt[g]), 1ull);
   }
+}
+
+// One batch of 4 * V keys: all gathers first, then all accumulations.
+template <int GROUPS, int V>
+__device__ __forceinline__ void join_batch(JoinCtx<GROUPS> &c, const i32x4 (&x)[V]) {
+  uint32_t w[V][4];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    w[u][0] = join_fetch(c, (uint32_t)x[u].x);
+    w[u][1] = join_fetch(c, (uint32_t)x[u].y);
+    w[u][2] = join_fetch(c, (uint32_t)x[u].z);
+    w[u][3] = join_fetch(c, (uint32_t)x[u].w);
+  }
+  uint32_t all = kValid;
+  uint32_t s32 = 0, c32 = 0;
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t wj = w[u][j];
+      all &= wj;
+      if (GROUPS == 16) {
+        const uint32_t bin = (wj >> kGroupShift) & (kJoinBins - 1);
+        lds_add_u64(&c.bins[bin * kWave + lane_id()], (1ull << kCountShift) | (wj & kPriceMask));
+      } else {
+        s32 += wj & kPriceMask;
+        c32 += (wj >> kGroupShift) & 1u;
+      }
+    }
+  }
+  if (GROUPS == 1) {
+    c.sum += s32;
+    c.cnt += c32;
+  }
+  if (__builtin_expect(!(all & kValid), 0)) {  // an escape or out-of-range key in this batch
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      if (!w[u][0]) join_slow(c, (uint32_t)x[u].x);
+      if (!w[u][1]) join_slow(c, (uint32_t)x[u].y);
+      if (!w[u][2]) join_slow(c, (uint32_t)x[u].z);
+      if (!w[u][3]) join_slow(c, (uint32_t)x[u].w);
+    }
+  }
+}
+
+template <int GROUPS>
+__device__ __forceinline__ void join_single(JoinCtx<GROUPS> &c, int32_t k) {
+  const uint32_t w = join_fetch(c, (uint32_t)k);
+  if (GROUPS == 16) {
+    lds_add_u64(&c.bins[((w >> kGroupShift) & (kJoinBins - 1)) * kWave + lane_id()],
+                (1ull << kCountShift) | (w & kPriceMask));
+  } else {
+    c.sum += w & kPriceMask;
+    c.cnt += (w >> kGroupShift) & 1u;
+  }
+  if (!w) join_slow(c, (uint32_t)k);
 }
 
 template <int GROUPS>
@@ -99,84 +192,83 @@ __global__ __launch_bounds__(kJoinThreads) void join_kernel(const int32_t *__res
                                                             int64_t *__restrict__ out_sum,
                                                             int64_t *__restrict__ out_cnt, int32_t *flag) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int kBinBytes = GROUPS == 16 ? 16 * kWave * 8 : 0;
+  constexpr int kBinBytes = GROUPS == 16 ? kJoinBins * kWave * 8 : 0;
+  JoinCtx<GROUPS> c;
+  c.bins = reinterpret_cast<uint64_t *>(smem);
   uint32_t *hot = reinterpret_cast<uint32_t *>(smem + kBinBytes);
-  JoinAcc<GROUPS> acc;
-  if (GROUPS == 16) {
-    acc.bins = reinterpret_cast<uint64_t *>(smem);
-    for (int i = threadIdx.x; i < 16 * kWave; i += blockDim.x) acc.bins[i] = 0;
-  }
+  c.hot = hot;
+  c.words = record_buffer(words, (uint32_t)n_rows);
+  c.t = (uint32_t)t_lds;
+  c.tclamp = t_lds > 0 ? (uint32_t)t_lds - 1 : 0u;  // LDS always holds at least one word
+  c.sum = 0;
+  c.cnt = 0;
+  c.price = price;
+  c.cat = cat;
+  c.cat_lt = cat_lt;
+  c.n_rows = (uint32_t)n_rows;
+  c.out_sum = out_sum;
+  c.out_cnt = out_cnt;
+  c.bad = false;
+  if (GROUPS == 16)
+    for (int i = threadIdx.x; i < kJoinBins * kWave; i += blockDim.x) c.bins[i] = 0;
   {  // stage the hot prefix (words is 256-byte aligned workspace)
     const int nv = t_lds >> 2;
     const uint4 *src = reinterpret_cast<const uint4 *>(words);
     uint4 *dst = reinterpret_cast<uint4 *>(hot);
     for (int i = threadIdx.x; i < nv; i += blockDim.x) dst[i] = src[i];
     for (int i = 4 * nv + threadIdx.x; i < t_lds; i += blockDim.x) hot[i] = words[i];
+    if (t_lds == 0 && threadIdx.x == 0) hot[0] = 0;
   }
   __syncthreads();
 
-  auto lookup = [&](int32_t k, uint32_t &w) -> bool {
-    if ((uint32_t)k < (uint32_t)t_lds) {
-      w = hot[k];
-    } else if ((uint32_t)k < (uint32_t)n_rows) {
-      w = words[k];
-    } else {
-      raise_flag(flag);
-      return false;
-    }
-    return true;
-  };
-  auto one = [&](int32_t k) {
-    uint32_t w;
-    if (lookup(k, w)) join_consume<GROUPS>(acc, w, k, price, cat, cat_lt, out_sum, out_cnt);
-  };
-
   const Split4 sp = split4(keys, n);
-  const int64_t T = (int64_t)gridDim.x * blockDim.x;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid < sp.head) one(keys[gid]);
-  if (gid < n - sp.tail) one(keys[sp.tail + gid]);
+  if (gid < sp.head) join_single(c, keys[gid]);
+  if (gid < n - sp.tail) join_single(c, keys[sp.tail + gid]);
+
+  // Full tiles of kJoinThreads * kJoinVecs vectors, two batches in flight:
+  // the next tile's keys are loaded while the current one is processed.
   const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
-  int64_t v = gid;
-  for (; v + (kJoinUnroll - 1) * T < sp.nvec; v += kJoinUnroll * T) {
-    i32x4 x[kJoinUnroll];
+  const int64_t tile_vecs = (int64_t)kJoinThreads * kJoinVecs;
+  const int64_t ntiles = sp.nvec / tile_vecs;
+  int64_t tile = blockIdx.x;
+  i32x4 xa[kJoinVecs], xb[kJoinVecs];
+  auto load_tile = [&](i32x4(&x)[kJoinVecs], int64_t tl) {
+    const i32x4 *p = vk + tl * tile_vecs + threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < kJoinUnroll; ++u) x[u] = load_stream4(vk + v + u * T);
-    uint32_t w[kJoinUnroll][4];
-    bool ok[kJoinUnroll][4];
-#pragma unroll
-    for (int u = 0; u < kJoinUnroll; ++u) {
-      ok[u][0] = lookup(x[u].x, w[u][0]);
-      ok[u][1] = lookup(x[u].y, w[u][1]);
-      ok[u][2] = lookup(x[u].z, w[u][2]);
-      ok[u][3] = lookup(x[u].w, w[u][3]);
-    }
-#pragma unroll
-    for (int u = 0; u < kJoinUnroll; ++u) {
-      if (ok[u][0]) join_consume<GROUPS>(acc, w[u][0], x[u].x, price, cat, cat_lt, out_sum, out_cnt);
-      if (ok[u][1]) join_consume<GROUPS>(acc, w[u][1], x[u].y, price, cat, cat_lt, out_sum, out_cnt);
-      if (ok[u][2]) join_consume<GROUPS>(acc, w[u][2], x[u].z, price, cat, cat_lt, out_sum, out_cnt);
-      if (ok[u][3]) join_consume<GROUPS>(acc, w[u][3], x[u].w, price, cat, cat_lt, out_sum, out_cnt);
-    }
+    for (int u = 0; u < kJoinVecs; ++u) x[u] = load_stream4(p + u * kJoinThreads);
+  };
+  // The prefetch is unconditional (the last one re-reads the current tile) so
+  // that every path has the same loads in flight and the wait before a batch
+  // covers only that batch's keys.
+  if (tile < ntiles) load_tile(xa, tile);
+  while (tile < ntiles) {
+    int64_t nxt = tile + gridDim.x;
+    load_tile(xb, nxt < ntiles ? nxt : tile);
+    join_batch<GROUPS, kJoinVecs>(c, xa);
+    tile = nxt;
+    if (tile >= ntiles) break;
+    nxt = tile + gridDim.x;
+    load_tile(xa, nxt < ntiles ? nxt : tile);
+    join_batch<GROUPS, kJoinVecs>(c, xb);
+    tile = nxt;
   }
-  for (; v < sp.nvec; v += T) {
-    const i32x4 x = load_stream4(vk + v);
-    one(x.x);
-    one(x.y);
-    one(x.z);
-    one(x.w);
+  for (int64_t v = ntiles * tile_vecs + gid; v < sp.nvec; v += (int64_t)gridDim.x * blockDim.x) {
+    const i32x4 x[1] = {load_stream4(vk + v)};
+    join_batch<GROUPS, 1>(c, x);
   }
+  if (c.bad) *flag = 1;
 
   // Workgroup reduction, then one global atomic per group.
   if (GROUPS == 1) {
     __shared__ uint64_t red_s[kJoinThreads / kWave];
     __shared__ uint32_t red_c[kJoinThreads / kWave];
-    const uint64_t s = wave_sum_u64(acc.sum);
-    const uint32_t c = wave_sum_u32(acc.cnt);
+    const uint64_t s = wave_sum_u64(c.sum);
+    const uint32_t k = wave_sum_u32(c.cnt);
     const int w = threadIdx.x / kWave;
     if (lane_id() == 0) {
       red_s[w] = s;
-      red_c[w] = c;
+      red_c[w] = k;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -192,14 +284,14 @@ __global__ __launch_bounds__(kJoinThreads) void join_kernel(const int32_t *__res
     }
   } else {
     __syncthreads();
-    const int g = threadIdx.x / kWave;  // 16 waves <-> 16 groups
+    const int g = threadIdx.x / kWave;  // 16 waves <-> 16 groups, bin g + 1
     if (g < 16) {
-      const uint64_t e = acc.bins[g * kWave + lane_id()];
+      const uint64_t e = c.bins[(g + 1) * kWave + lane_id()];
       const uint64_t s = wave_sum_u64(e & kSumMask);
-      const uint64_t c = wave_sum_u64(e >> kCountShift);
-      if (lane_id() == 0 && c) {
+      const uint64_t k = wave_sum_u64(e >> kCountShift);
+      if (lane_id() == 0 && k) {
         global_add_u64(reinterpret_cast<uint64_t *>(&out_sum[g]), s);
-        global_add_u64(reinterpret_cast<uint64_t *>(&out_cnt[g]), c);
+        global_add_u64(reinterpret_cast<uint64_t *>(&out_cnt[g]), k);
       }
     }
   }
@@ -229,7 +321,7 @@ struct GroupCtx {
   int32_t ncopy;  // range mode: groups [0, ncopy) have per-lane copies, ncopy = min(t, kGroupCopies)
   uint64_t *acc_sum;
   uint64_t *acc_cnt;
-  int32_t *flag;
+  bool bad;
   // range mode
   uint64_t *copy_sum;  // [kGroupCopies][64]
   uint32_t *copy_cnt;
@@ -247,9 +339,9 @@ __device__ __forceinline__ void group_global(const GroupCtx &c, int32_t g, int32
 }
 
 template <int MODE>
-__device__ __forceinline__ void group_one(const GroupCtx &c, int32_t g, int32_t v) {
+__device__ __forceinline__ void group_one(GroupCtx &c, int32_t g, int32_t v) {
   if ((uint32_t)g >= (uint32_t)c.m) {
-    raise_flag(c.flag);
+    c.bad = true;
     return;
   }
   if (MODE == kGroupRange) {
@@ -297,7 +389,7 @@ __global__ __launch_bounds__(kGroupThreads) void group_kernel(const int32_t *__r
   c.ncopy = t < kGroupCopies ? t : kGroupCopies;
   c.acc_sum = acc_sum;
   c.acc_cnt = acc_cnt;
-  c.flag = flag;
+  c.bad = false;
   if (MODE == kGroupRange) {
     c.copy_sum = reinterpret_cast<uint64_t *>(smem);
     c.bin_sum = c.copy_sum + kGroupCopies * kWave;
@@ -361,6 +453,7 @@ __global__ __launch_bounds__(kGroupThreads) void group_kernel(const int32_t *__r
   } else {
     for (int64_t i = gid; i < n; i += T) group_one<MODE>(c, load_stream1(keys + i), load_stream1(vals + i));
   }
+  if (c.bad) *flag = 1;
   __syncthreads();
 
   // Flush the private bins into the shared accumulators.
@@ -426,11 +519,12 @@ void allow_lds(K kernel, size_t bytes) {
 // Capacities and launchers
 // ---------------------------------------------------------------------------
 size_t join_lds_bytes(int groups, int32_t hot_rows) {
-  return (groups == 16 ? 16 * kWave * 8 : 0) + (size_t)hot_rows * 4;
+  const size_t hot = hot_rows > 0 ? ((size_t)hot_rows * 4 + 15) & ~(size_t)15 : 16;
+  return (groups == 16 ? (size_t)kJoinBins * kWave * 8 : 0) + hot;
 }
 
 int32_t join_max_hot_rows(int groups, const DeviceInfo &dev) {
-  const size_t fixed = join_lds_bytes(groups, 0) + 256;  // static reduction scratch
+  const size_t fixed = join_lds_bytes(groups, 0) - 16 + 256;  // bins + static reduction scratch
   if (dev.lds_per_block <= fixed) return 0;
   return (int32_t)(((dev.lds_per_block - fixed) / 4) & ~(size_t)3);
 }
