@@ -32,7 +32,8 @@ METRIC = "fact tuples/s and % of HBM roofline, skew layout vs identity layout (b
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "join_kernel_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1910_10063_amd", "csrc", f)
-                  for f in ("query_kernels.hip", "device_common.h", "kernels.h")]
+                  for f in ("join_kernels.hip", "partition_kernels.hip", "query_common.h", "device_common.h",
+                            "kernels.h")]
 
 
 def log(msg):
@@ -132,11 +133,10 @@ def main():
     jws = skew.workspace(skew.SKEW_OP_JOIN, F, N, dev)
     out_s = torch.empty(16, dtype=torch.int64, device=dev)
     out_c = torch.empty(16, dtype=torch.int64, device=dev)
-    empty = torch.empty(0, dtype=torch.int32, device=dev)
     t_hot = args.hot_rows
 
-    def query(keys, pr, ca, t):
-        return lambda: skew.fk_join_aggregate(keys, pr, ca, 16, True, hot_rows=t, ws=jws, out=(out_s, out_c))
+    def query(keys, pr, ca, t, ws=jws):
+        return lambda: skew.fk_join_aggregate(keys, pr, ca, 16, True, hot_rows=t, ws=ws, out=(out_s, out_c))
 
     log("skew-layout query (timed steps)")
     ms_skew = timed(query(Cp, pp, cp, t_hot), K, WU, stream)
@@ -144,24 +144,54 @@ def main():
     log("identity-layout query")
     ms_ident = timed(query(C, price, cat, 0), K, WU, stream)
     ident_res = (out_s.cpu().numpy().copy(), out_c.cpu().numpy().copy())
-    ms_pack = timed(query(empty, pp, cp, t_hot), K, WU, stream)  # dimension pack only (empty fact column)
-    ms_join_kernel = max(ms_skew - ms_pack, 1e-6)
-    ms_join_kernel_ident = max(ms_ident - ms_pack, 1e-6)
     agree = bool((skew_res[0] == ident_res[0]).all() and (skew_res[1] == ident_res[1]).all())
 
-    # roofline of the dominant kernel (join-aggregate): algorithmic bytes = 4 B per fact key
-    # plus 4 B per packed dimension word read once
-    alg_bytes = 4.0 * F + 4.0 * N
-    achieved = alg_bytes / (ms_join_kernel * 1e-3) / 1e9
+    # ---- per-stage times from HIP events recorded by the library on this stream
+    KP = max(K // 2, 3)
+    skew.profile_report()
+    skew.profile_enable(True)
+    for _ in range(KP):
+        query(Cp, pp, cp, t_hot)()
+    st_skew = skew.profile_report()
+    for _ in range(KP):
+        query(C, price, cat, 0)()
+    st_ident = skew.profile_report()
+    build()
+    st_build = skew.profile_report()
+    skew.profile_enable(False)
+
+    def per_query(st, n):
+        return {k: {"ms": round(v[0] / n, 4), "launches": round(v[1] / n, 3)} for k, v in st.items()}
+
+    stages_skew = per_query(st_skew, KP)
+    stages_ident = per_query(st_ident, KP)
+    # dominant kernel of the skew query; algorithmic bytes per launch: 4 B per fact key it streams
+    # plus 4 B per hot dimension word it stages (pass 1 / single pass), 9 B per dimension row (pack)
+    dom = max(stages_skew, key=lambda k: stages_skew[k]["ms"])
+    launches = stages_skew[dom]["launches"]
+    hot_used = min(skew.max_hot_rows(True), N) if t_hot < 0 else min(t_hot, N)
+    if dom in ("join_split", "join_single_pass"):
+        dom_bytes = 4.0 * F / launches + 4.0 * hot_used
+    elif dom == "join_pack":
+        dom_bytes = 9.0 * N
+    else:
+        dom_bytes = 4.0 * F / launches
+    dom_ms = stages_skew[dom]["ms"] / launches
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("source_sha") == kernel_source_sha() and tr.get("n_fact") == F and tr.get("n_rows") == N \
-                and tr.get("zipf_s") == S:
+        if tr.get("source_sha") == kernel_source_sha() and tr.get("kernel") == dom and tr.get("n_fact") == F \
+                and tr.get("n_rows") == N and tr.get("zipf_s") == S:
             traffic = tr.get("hbm_bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": "join_kernel<16>", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": alg_bytes, "kernel_ms": round(ms_join_kernel, 4)}
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": dom_bytes, "kernel_ms": round(dom_ms, 4),
+                "launches_per_query": launches}
+    q_bytes = 4.0 * F + 9.0 * N  # whole query: every fact key once, both dimension columns once
+    query_roofline = {"bound": "hbm", "algorithmic_bytes": q_bytes,
+                      "achieved": round(q_bytes / (ms_skew * 1e-3) / 1e9, 1),
+                      "frac": round(q_bytes / (ms_skew * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     result = {
         "metric": METRIC,
@@ -179,18 +209,24 @@ def main():
         "config": {"workload": f"fk-join-aggregate: {N:.0e}-row dimension, {F:.0e} Zipf(s={S}) int32 fact keys, "
                                "SUM(price), COUNT(*) GROUP BY category (16 groups), skew layout",
                    "n_rows": N, "n_fact": F, "zipf_s": S, "groups": 16, "hot_rows": t_hot,
-                   "hot_rows_used": min(skew.max_hot_rows(True), N) if t_hot < 0 else min(t_hot, N),
+                   "hot_rows_used": hot_used,
                    "seeds": {"fact": W.fact_seed(k), "perm": W.perm_seed(k), "price": W.price_seed(k),
                              "category": W.category_seed(k)}},
         "roofline": roofline,
-        "identity": {"value": F / (ms_ident * 1e-3), "ms_per_step": ms_ident,
-                     "kernel_gbs": round(alg_bytes / (ms_join_kernel_ident * 1e-3) / 1e9, 1)},
+        "query_roofline": query_roofline,
+        "identity": {"value": F / (ms_ident * 1e-3), "ms_per_step": ms_ident},
         "speedup_vs_identity": ms_ident / ms_skew,
-        "pack_ms": ms_pack,
+        "stages_ms": {"skew": stages_skew, "identity": stages_ident, "build": per_query(st_build, 1)},
         "build": {"ms": build_ms, "fact_tuples_per_s": F / (build_ms * 1e-3)},
         "layouts_agree": agree,
     }
 
+    if not args.no_extras:
+        single_ws = skew.workspace(skew.SKEW_OP_JOIN_SINGLE_PASS, F, N, dev)
+        ms_sp = timed(query(Cp, pp, cp, t_hot, single_ws), max(K // 2, 3), 1, stream)
+        ms_sp_i = timed(query(C, price, cat, 0, single_ws), max(K // 2, 3), 1, stream)
+        result["single_pass"] = {"skew_tuples_per_s": F / (ms_sp * 1e-3), "identity_tuples_per_s": F / (ms_sp_i * 1e-3)}
+        del single_ws
     if not args.no_extras:
         # hot-prefix sweep (rows above the LDS capacity are served from L2: same as the capacity)
         cap = skew.max_hot_rows(True)
@@ -244,23 +280,34 @@ def bench_group_by(K, WU, dev, stream):
     torch.cuda.synchronize()
     build_s = time.time() - t0
     gws = skew.workspace(skew.SKEW_OP_GROUP, F, M, dev)
+    gws1 = skew.workspace(skew.SKEW_OP_GROUP_SINGLE_PASS, F, M, dev)
     out = (torch.empty(M, dtype=torch.int64, device=dev), torch.empty(M, dtype=torch.int64, device=dev))
     res = {}
-    for name, keys, t, perm in (("skew", L.fact_recoded, skew.SKEW_HOT_AUTO, L.perm),
-                                ("identity_hash", G, 0, None),
-                                ("identity_atomic", G, skew.SKEW_HOT_NONE, None)):
+    runs = (("skew", L.fact_recoded, skew.SKEW_HOT_AUTO, L.perm, gws),
+            ("identity", G, 0, None, gws),                       # partitioned, no id-based privatisation
+            ("skew_single_pass", L.fact_recoded, skew.SKEW_HOT_AUTO, L.perm, gws1),
+            ("identity_hash_single_pass", G, 0, None, gws1),
+            ("identity_atomic", G, skew.SKEW_HOT_NONE, None, gws1))
+    for name, keys, t, perm, ws in runs:
         steps = K if name != "identity_atomic" else max(K // 4, 2)
-        ms = timed(lambda: skew.group_aggregate(keys, V, M, hot_groups=t, perm=perm, ws=gws, out=out), steps,
+        ms = timed(lambda: skew.group_aggregate(keys, V, M, hot_groups=t, perm=perm, ws=ws, out=out), steps,
                    1, stream)
         res[name] = {"ms": ms, "tuples_per_s": F / (ms * 1e-3),
                      "sum_digest": hashlib.sha256(out[0].cpu().numpy().tobytes() +
                                                   out[1].cpu().numpy().tobytes()).hexdigest()[:16]}
+    skew.profile_report()
+    skew.profile_enable(True)
+    for _ in range(3):
+        skew.group_aggregate(L.fact_recoded, V, M, hot_groups=skew.SKEW_HOT_AUTO, perm=L.perm, ws=gws, out=out)
+    st = skew.profile_report()
+    skew.profile_enable(False)
+    stages = {k: {"ms": round(v[0] / 3, 4), "launches": round(v[1] / 3, 3)} for k, v in st.items()}
     alg = 8.0 * F + 16.0 * M
     ms = res["skew"]["ms"]
     return {"workload": f"group-aggregate: {M:.0e} groups, {F:.0e} rows, Zipf(s={s}) keys, values U[0,1000]",
-            "skew": res["skew"], "identity_hash": res["identity_hash"], "identity_atomic": res["identity_atomic"],
-            "speedup_vs_identity_hash": res["identity_hash"]["ms"] / ms,
-            "roofline_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "runs": res, "speedup_vs_identity": res["identity"]["ms"] / ms,
+            "speedup_vs_best_identity": min(r["ms"] for n, r in res.items() if n.startswith("identity")) / ms,
+            "roofline_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "stages_ms": stages,
             "build_s_incl_sync": build_s,
             "layouts_agree": len({r["sum_digest"] for r in res.values()}) == 1}
 

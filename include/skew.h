@@ -40,10 +40,17 @@ extern "C" {
 #define SKEW_EHIP (-4)     /* HIP runtime or launch failure */
 #define SKEW_EDEVICE (-5)  /* no usable gfx950 device */
 
-/* Operation ids for skew_workspace_bytes. */
+/* Operation ids for skew_workspace_bytes.  SKEW_OP_JOIN / SKEW_OP_GROUP give
+ * the size that enables the partitioned form of the query (cold rows buffered,
+ * partitioned by slice and resolved from LDS in a second pass) for inputs of
+ * at least 2^22 rows; the *_SINGLE_PASS sizes are the minimum, with which the
+ * single-pass kernels run.  A query uses the partitioned form whenever the
+ * workspace it is given is large enough for it. */
 #define SKEW_OP_BUILD 1
 #define SKEW_OP_JOIN 2
 #define SKEW_OP_GROUP 3
+#define SKEW_OP_JOIN_SINGLE_PASS 4
+#define SKEW_OP_GROUP_SINGLE_PASS 5
 
 /* hot_rows / hot_groups special values. */
 #define SKEW_HOT_AUTO (-1)  /* library picks the hot prefix from LDS capacity */
@@ -104,7 +111,11 @@ int build_skew_layout(const int32_t *fact_keys, int64_t n_fact, int32_t n_keys, 
  *                         LDS capacity); 0 = every row read from global memory
  *                         (the identity-layout method); SKEW_HOT_AUTO.
  *   out_sum, out_count    out: int64[1] or int64[16].
- *   workspace             >= skew_workspace_bytes(SKEW_OP_JOIN, n_fact, n_rows).
+ *   workspace             >= skew_workspace_bytes(SKEW_OP_JOIN_SINGLE_PASS, ...);
+ *                         with skew_workspace_bytes(SKEW_OP_JOIN, n_fact, n_rows)
+ *                         bytes the keys at or above t are buffered, partitioned
+ *                         into slices of 32768 rows and resolved from LDS copies
+ *                         of the slices (Section 4.2.1's second pass).
  *
  * Fact keys outside [0, n_rows) join nothing and set the workspace's error
  * flag (see skew_query_status).  The answer does not depend on t or on the
@@ -126,15 +137,20 @@ int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *d
  *   values[n_fact]      int32 values.
  *   n_groups            >= 1.
  *   hot_groups          t > 0: groups [0, t) are aggregated in per-workgroup LDS
- *                       bins (clamped to capacity), the rest with global
- *                       atomics; 0: layout-oblivious LDS hash privatisation
- *                       (the identity-layout method); SKEW_HOT_NONE: global
- *                       atomics only; SKEW_HOT_AUTO.
+ *                       bins (clamped to capacity); the rest are either
+ *                       partitioned into slices of 8192 groups and summed in
+ *                       LDS (workspace of SKEW_OP_GROUP size) or sent to global
+ *                       atomics (single-pass workspace).  0: no id-based
+ *                       privatisation, the layout-oblivious method: every row
+ *                       partitioned (large workspace) or an LDS hash table of
+ *                       the first groups met (single pass).  SKEW_HOT_NONE:
+ *                       global atomics only.  SKEW_HOT_AUTO: LDS capacity.
  *   perm[n_groups]      nullable.  If set, group_keys are ranks and the
  *                       outputs are returned in original-key order:
  *                       out[perm[r]] = aggregate of rank r.
  *   out_sum, out_count  out: int64[n_groups].
- *   workspace           >= skew_workspace_bytes(SKEW_OP_GROUP, n_fact, n_groups).
+ *   workspace           >= skew_workspace_bytes(SKEW_OP_GROUP_SINGLE_PASS, ...);
+ *                       SKEW_OP_GROUP size enables the partitioned form.
  *
  * Rows whose key is outside [0, n_groups) are skipped and set the error flag.
  */
@@ -148,6 +164,16 @@ int group_aggregate(const int32_t *group_keys, const int32_t *values, int64_t n_
  * out-of-range key (SKEW_ERANGE) or not (SKEW_OK).
  */
 int skew_query_status(const void *workspace, size_t workspace_bytes, void *stream);
+
+/* Stage timing, for benchmarks.  While enabled (on != 0), every launch stage
+ * of the calls above (e.g. "join_split", "join_partition", "join_slice",
+ * "build_histogram") records a pair of HIP events on the stream it runs on.
+ * skew_profile_report waits for them, writes up to max_stages entries (stage
+ * names as consecutive NUL-terminated strings in names[names_bytes], total
+ * milliseconds in ms[], number of launches in calls[]), forgets them, and
+ * returns the number of entries.  Off by default; costs two events per stage. */
+void skew_profile_enable(int on);
+int skew_profile_report(char *names, int names_bytes, float *ms, int *calls, int max_stages);
 
 /* Hot-prefix capacities (rows / groups) the kernels can hold in LDS on the
  * current device, or a negative code. */

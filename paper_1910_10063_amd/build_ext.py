@@ -33,7 +33,8 @@ FLAGS = [
 ]
 
 TARGETS = {
-    "libskew.so": ["skew_api.hip", "layout_kernels.hip", "query_kernels.hip"],
+    "libskew.so": ["skew_api.hip", "layout_kernels.hip", "partition_kernels.hip", "join_kernels.hip",
+                   "group_kernels.hip"],
     "libskewgen.so": ["workload_gen.hip"],
 }
 

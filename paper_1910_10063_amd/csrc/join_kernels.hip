@@ -1,0 +1,730 @@
+// FK join-aggregate (Q1/Q2 of Section 1 feeding SUM/COUNT) with
+// threshold-based processing (Section 4.2): dimension rows [0, t) are copied
+// into LDS once per workgroup and keys below t are resolved there.  Keys at or
+// above t are either gathered from global memory (single pass) or written to
+// a cold buffer, partitioned by dimension slice and resolved from LDS copies
+// of the slices in a second pass (the threshold split of Section 4.2.1).
+#include "kernels.h"
+#include "profiler.h"
+#include "query_common.h"
+
+namespace skew {
+namespace {
+
+__global__ void join_pack_kernel(const int32_t *__restrict__ price, const int8_t *__restrict__ cat, int32_t n_rows,
+                                 int32_t cat_lt, int32_t by_cat, uint32_t *__restrict__ words,
+                                 int64_t *__restrict__ out_sum, int64_t *__restrict__ out_cnt, int32_t *flag) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < (by_cat ? 16 : 1)) {
+    out_sum[gid] = 0;
+    out_cnt[gid] = 0;
+  }
+  if (gid == 0) *flag = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = gid; r < n_rows; r += stride) {
+    const int32_t p = price[r];
+    int32_t g;
+    uint32_t w = kValid;
+    if (row_group(cat[r], cat_lt, by_cat, &g))
+      w = ((uint32_t)p <= kPriceMask) ? (kValid | ((uint32_t)(g + 1) << kGroupShift) | (uint32_t)p) : 0u;
+    words[r] = w;
+  }
+}
+
+constexpr int kJoinVecs = 4;  // 16-byte key vectors per lane per batch
+
+// Accumulators.  GROUPS == 16: every lane owns one 64-bit bin per group in
+// LDS, shared by the 16 waves of the workgroup through LDS atomics (two lanes
+// of a wave never hit the same bin); a bin packs count << 44 | sum and stays
+// exact while it sees fewer than 2^19 rows (enforced per launch).
+// GROUPS == 1: sums in registers.
+template <int GROUPS>
+struct JoinCtx {
+  uint64_t *bins;  // LDS [kJoinBins][64]
+  uint64_t sum;
+  uint32_t cnt;
+  bool bad;
+  // slow path (price outside [0, 2^25) or key outside the dimension)
+  const int32_t *price;
+  const int8_t *cat;
+  int32_t cat_lt;
+  uint32_t n_rows;
+  int64_t *out_sum, *out_cnt;
+};
+
+template <int GROUPS>
+__device__ __forceinline__ void join_init(JoinCtx<GROUPS> &c, unsigned char *smem, const int32_t *price,
+                                          const int8_t *cat, int32_t cat_lt, int32_t n_rows, int64_t *out_sum,
+                                          int64_t *out_cnt) {
+  c.bins = reinterpret_cast<uint64_t *>(smem);
+  c.sum = 0;
+  c.cnt = 0;
+  c.bad = false;
+  c.price = price;
+  c.cat = cat;
+  c.cat_lt = cat_lt;
+  c.n_rows = (uint32_t)n_rows;
+  c.out_sum = out_sum;
+  c.out_cnt = out_cnt;
+  if (GROUPS == 16)
+    for (int i = threadIdx.x; i < kJoinBins * kWave; i += blockDim.x) c.bins[i] = 0;
+}
+
+template <int GROUPS>
+__device__ __forceinline__ void join_add(JoinCtx<GROUPS> &c, uint32_t w) {
+  if (GROUPS == 16) {
+    const uint32_t bin = (w >> kGroupShift) & (kJoinBins - 1);
+    lds_add_u64(&c.bins[bin * kWave + lane_id()], (1ull << kCountShift) | (w & kPriceMask));
+  } else {
+    c.sum += w & kPriceMask;
+    c.cnt += (w >> kGroupShift) & 1u;
+  }
+}
+
+template <int GROUPS>
+__device__ __forceinline__ void join_slow(JoinCtx<GROUPS> &c, uint32_t uk) {
+  if (uk >= c.n_rows) {
+    c.bad = true;
+    return;
+  }
+  int32_t g;
+  if (row_group(c.cat[uk], c.cat_lt, GROUPS == 16, &g)) {
+    global_add_u64(reinterpret_cast<uint64_t *>(&c.out_sum[g]), (uint64_t)(int64_t)c.price[uk]);
+    global_add_u64(reinterpret_cast<uint64_t *>(&c.out_cnt[g]), 1ull);
+  }
+}
+
+// Workgroup reduction of the accumulators, then one global atomic per group.
+template <int GROUPS>
+__device__ __forceinline__ void join_flush(JoinCtx<GROUPS> &c, int32_t *flag) {
+  if (c.bad) *flag = 1;
+  if (GROUPS == 1) {
+    __shared__ uint64_t red_s[kJoinThreads / kWave];
+    __shared__ uint32_t red_c[kJoinThreads / kWave];
+    const uint64_t s = wave_sum_u64(c.sum);
+    const uint32_t k = wave_sum_u32(c.cnt);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+      red_s[w] = s;
+      red_c[w] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t ts = 0, tc = 0;
+      for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+        ts += red_s[i];
+        tc += red_c[i];
+      }
+      if (tc) {
+        global_add_u64(reinterpret_cast<uint64_t *>(&c.out_sum[0]), ts);
+        global_add_u64(reinterpret_cast<uint64_t *>(&c.out_cnt[0]), tc);
+      }
+    }
+  } else {
+    __syncthreads();
+    const int g = threadIdx.x / kWave;  // 16 waves <-> 16 groups, bin g + 1
+    if (g < 16) {
+      const uint64_t e = c.bins[(g + 1) * kWave + lane_id()];
+      const uint64_t s = wave_sum_u64(e & kSumMask);
+      const uint64_t k = wave_sum_u64(e >> kCountShift);
+      if (lane_id() == 0 && k) {
+        global_add_u64(reinterpret_cast<uint64_t *>(&c.out_sum[g]), s);
+        global_add_u64(reinterpret_cast<uint64_t *>(&c.out_cnt[g]), k);
+      }
+    }
+  }
+}
+
+// Copy dimension words [base, base + len) into LDS (words is 256-byte aligned
+// workspace; base is a multiple of 4 whenever len > 3).
+__device__ __forceinline__ void stage_words(uint32_t *dst, const uint32_t *words, int64_t base, int32_t len) {
+  const uint32_t *src = words + base;
+  if ((base & 3) == 0) {
+    const int nv = len >> 2;
+    for (int i = threadIdx.x; i < nv; i += blockDim.x)
+      reinterpret_cast<uint4 *>(dst)[i] = reinterpret_cast<const uint4 *>(src)[i];
+    for (int i = 4 * nv + threadIdx.x; i < len; i += blockDim.x) dst[i] = src[i];
+  } else {
+    for (int i = threadIdx.x; i < len; i += blockDim.x) dst[i] = src[i];
+  }
+}
+
+// Hot prefix + cold lookup state of the single-pass kernel.
+struct HotCtx {
+  const uint32_t *hot;  // LDS
+  rsrc_t words;
+  uint32_t t, tclamp;
+};
+
+__device__ __forceinline__ uint32_t fetch_hot_or_global(const HotCtx &h, uint32_t uk) {
+  // Two reads without branching: a clamped LDS read and a buffer gather whose
+  // index is pushed out of range for hot keys (it returns 0 and issues no
+  // memory traffic); the select keeps the right one.
+  const bool hot = uk < h.t;
+  const uint32_t wl = h.hot[uk < h.tclamp ? uk : h.tclamp];
+  const uint32_t wg = buffer_load_record(h.words, (int32_t)(hot ? 0xFFFFFFFFu : uk), 0, 0, 0);
+  return hot ? wl : wg;
+}
+
+// ---------------------------------------------------------------------------
+// Single pass: one workgroup of 1024 threads per CU, grid-stride over tiles of
+// 1024 x kJoinVecs key vectors, the next tile loaded while the current one is
+// processed.
+// ---------------------------------------------------------------------------
+template <int GROUPS, int V>
+__device__ __forceinline__ void join_batch(JoinCtx<GROUPS> &c, const HotCtx &h, const i32x4 (&x)[V]) {
+  uint32_t w[V][4];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    w[u][0] = fetch_hot_or_global(h, (uint32_t)x[u].x);
+    w[u][1] = fetch_hot_or_global(h, (uint32_t)x[u].y);
+    w[u][2] = fetch_hot_or_global(h, (uint32_t)x[u].z);
+    w[u][3] = fetch_hot_or_global(h, (uint32_t)x[u].w);
+  }
+  uint32_t all = kValid;
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      all &= w[u][j];
+      join_add(c, w[u][j]);
+    }
+  }
+  if (__builtin_expect(!(all & kValid), 0)) {  // an escape or out-of-range key in this batch
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      if (!w[u][0]) join_slow(c, (uint32_t)x[u].x);
+      if (!w[u][1]) join_slow(c, (uint32_t)x[u].y);
+      if (!w[u][2]) join_slow(c, (uint32_t)x[u].z);
+      if (!w[u][3]) join_slow(c, (uint32_t)x[u].w);
+    }
+  }
+}
+
+template <int GROUPS>
+__device__ __forceinline__ void join_single(JoinCtx<GROUPS> &c, const HotCtx &h, int32_t k) {
+  const uint32_t w = fetch_hot_or_global(h, (uint32_t)k);
+  join_add(c, w);
+  if (!w) join_slow(c, (uint32_t)k);
+}
+
+template <int GROUPS>
+__global__ __launch_bounds__(kJoinThreads) void join_kernel(const int32_t *__restrict__ keys, int64_t n,
+                                                            const uint32_t *__restrict__ words, int32_t n_rows,
+                                                            int32_t t_lds, const int32_t *__restrict__ price,
+                                                            const int8_t *__restrict__ cat, int32_t cat_lt,
+                                                            int64_t *__restrict__ out_sum,
+                                                            int64_t *__restrict__ out_cnt, int32_t *flag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int kBinBytes = GROUPS == 16 ? kJoinBins * kWave * 8 : 0;
+  JoinCtx<GROUPS> c;
+  join_init(c, smem, price, cat, cat_lt, n_rows, out_sum, out_cnt);
+  uint32_t *hot = reinterpret_cast<uint32_t *>(smem + kBinBytes);
+  HotCtx h;
+  h.hot = hot;
+  h.words = record_buffer(words, (uint32_t)n_rows);
+  h.t = (uint32_t)t_lds;
+  h.tclamp = t_lds > 0 ? (uint32_t)t_lds - 1 : 0u;  // LDS always holds at least one word
+  stage_words(hot, words, 0, t_lds);
+  if (t_lds == 0 && threadIdx.x == 0) hot[0] = 0;
+  __syncthreads();
+
+  const Split4 sp = split4(keys, n);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < sp.head) join_single(c, h, keys[gid]);
+  if (gid < n - sp.tail) join_single(c, h, keys[sp.tail + gid]);
+
+  // The prefetch is unconditional (the last one re-reads the current tile) so
+  // that every path has the same loads in flight and the wait before a batch
+  // covers only that batch's keys.
+  const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
+  const int64_t tile_vecs = (int64_t)kJoinThreads * kJoinVecs;
+  const int64_t ntiles = sp.nvec / tile_vecs;
+  int64_t tile = blockIdx.x;
+  i32x4 xa[kJoinVecs], xb[kJoinVecs];
+  auto load_tile = [&](i32x4(&x)[kJoinVecs], int64_t tl) {
+    const i32x4 *p = vk + tl * tile_vecs + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kJoinVecs; ++u) x[u] = load_stream4(p + u * kJoinThreads);
+  };
+  if (tile < ntiles) load_tile(xa, tile);
+  while (tile < ntiles) {
+    int64_t nxt = tile + gridDim.x;
+    load_tile(xb, nxt < ntiles ? nxt : tile);
+    join_batch<GROUPS, kJoinVecs>(c, h, xa);
+    tile = nxt;
+    if (tile >= ntiles) break;
+    nxt = tile + gridDim.x;
+    load_tile(xa, nxt < ntiles ? nxt : tile);
+    join_batch<GROUPS, kJoinVecs>(c, h, xb);
+    tile = nxt;
+  }
+  for (int64_t v = ntiles * tile_vecs + gid; v < sp.nvec; v += (int64_t)gridDim.x * blockDim.x) {
+    const i32x4 x[1] = {load_stream4(vk + v)};
+    join_batch<GROUPS, 1>(c, h, x);
+  }
+  join_flush(c, flag);
+}
+
+// ---------------------------------------------------------------------------
+// Partitioned form, pass 1: keys below t are resolved from LDS; every other
+// key inside the dimension is appended to this workgroup's segment of the
+// cold buffer and counted in its slice ((k - t) >> wshift).  Workgroup b
+// owns a contiguous range of the column, so its segment needs no more slots
+// than the rows it reads.
+// ---------------------------------------------------------------------------
+struct ColdSink {
+  int32_t *seg;         // this workgroup's segment
+  int64_t seg_cap;
+  uint32_t *count;      // LDS: items written so far
+  uint32_t *hist;       // LDS [P]
+  uint32_t t;
+  int32_t wshift;
+};
+
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t *count, uint32_t n) {
+  // One LDS atomic per wave: the first active lane reserves n slots.
+  uint32_t base = 0;
+  const uint64_t act = __ballot(1);
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  if (lane_id() == leader) base = atomicAdd(count, n);
+  return __shfl(base, leader, kWave);
+}
+
+template <int GROUPS, int V, bool GUARD>
+__device__ __forceinline__ void join_split_batch(JoinCtx<GROUPS> &c, const ColdSink &o, const uint32_t *hot,
+                                                 uint32_t tclamp, const i32x4 (&x)[V], const bool (&valid)[V]) {
+  uint32_t w[V][4], kk[V][4];
+  bool cold[V][4];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    kk[u][0] = (uint32_t)x[u].x, kk[u][1] = (uint32_t)x[u].y, kk[u][2] = (uint32_t)x[u].z, kk[u][3] = (uint32_t)x[u].w;
+  }
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t k = kk[u][j];
+      const bool ok = !GUARD || valid[u];
+      const bool h = ok && k < o.t;
+      cold[u][j] = ok && !h && k < c.n_rows;
+      if (ok && k >= c.n_rows) c.bad = true;
+      const uint32_t wl = hot[k < tclamp ? k : tclamp];
+      w[u][j] = h ? wl : kValid;
+    }
+  }
+  uint32_t all = kValid;
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      all &= w[u][j];
+      join_add(c, w[u][j]);
+    }
+  }
+  if (__builtin_expect(!(all & kValid), 0)) {  // a hot row whose price needs the slow path
+#pragma unroll
+    for (int u = 0; u < V; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (!w[u][j]) join_slow(c, kk[u][j]);
+  }
+  // Compact the cold keys: slot order within the wave, one reservation per wave.
+  uint64_t m[V][4];
+  uint32_t total = 0;
+#pragma unroll
+  for (int u = 0; u < V; ++u)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      m[u][j] = __ballot(cold[u][j]);
+      total += (uint32_t)__popcll(m[u][j]);
+    }
+  if (total == 0) return;
+  uint32_t pos = wave_reserve(o.count, total);
+  const uint64_t lt = (1ull << lane_id()) - 1ull;
+#pragma unroll
+  for (int u = 0; u < V; ++u)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (cold[u][j]) {
+        const uint32_t idx = pos + (uint32_t)__popcll(m[u][j] & lt);
+        const uint32_t k = kk[u][j];
+        if (idx < o.seg_cap) o.seg[idx] = (int32_t)k;
+        lds_add_u32(&o.hist[(k - o.t) >> o.wshift], 1u);
+      }
+      pos += (uint32_t)__popcll(m[u][j]);
+    }
+}
+
+template <int GROUPS>
+__device__ __forceinline__ void join_split_one(JoinCtx<GROUPS> &c, const ColdSink &o, const uint32_t *hot,
+                                               uint32_t tclamp, bool valid, uint32_t k) {
+  const bool h = valid && k < o.t;
+  const bool cd = valid && !h && k < c.n_rows;
+  if (valid && k >= c.n_rows) c.bad = true;
+  const uint32_t w = h ? hot[k < tclamp ? k : tclamp] : kValid;
+  join_add(c, w);
+  if (!w) join_slow(c, k);
+  const uint64_t m = __ballot(cd);
+  if (m) {
+    const uint32_t base = wave_reserve(o.count, (uint32_t)__popcll(m));
+    if (cd) {
+      const uint32_t idx = base + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
+      if (idx < o.seg_cap) o.seg[idx] = (int32_t)k;
+      lds_add_u32(&o.hist[(k - o.t) >> o.wshift], 1u);
+    }
+  }
+}
+
+template <int GROUPS>
+__global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
+    const int32_t *__restrict__ keys, int64_t n, const uint32_t *__restrict__ words, int32_t n_rows, int32_t t_lds,
+    int32_t P, int32_t wshift, const int32_t *__restrict__ price, const int8_t *__restrict__ cat, int32_t cat_lt,
+    int64_t *__restrict__ out_sum, int64_t *__restrict__ out_cnt, int32_t *flag, int32_t *__restrict__ cold_seg,
+    int64_t seg_cap, uint32_t *__restrict__ seg_count, uint32_t *__restrict__ hist) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int kBinBytes = GROUPS == 16 ? kJoinBins * kWave * 8 : 0;
+  JoinCtx<GROUPS> c;
+  join_init(c, smem, price, cat, cat_lt, n_rows, out_sum, out_cnt);
+  uint32_t *hot = reinterpret_cast<uint32_t *>(smem + kBinBytes);
+  const int32_t hot_words = (t_lds + 4) & ~3;  // at least one word, 16-byte multiple
+  uint32_t *lhist = hot + hot_words;
+  uint32_t *lcount = lhist + P;
+  stage_words(hot, words, 0, t_lds);
+  if (t_lds == 0 && threadIdx.x == 0) hot[0] = 0;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) lhist[p] = 0;
+  if (threadIdx.x == 0) *lcount = 0;
+  __syncthreads();
+
+  ColdSink o;
+  o.seg = cold_seg + (int64_t)blockIdx.x * seg_cap;
+  o.seg_cap = seg_cap;
+  o.count = lcount;
+  o.hist = lhist;
+  o.t = (uint32_t)t_lds;
+  o.wshift = wshift;
+  const uint32_t tclamp = t_lds > 0 ? (uint32_t)t_lds - 1 : 0u;
+
+  // Contiguous range of key vectors per workgroup; block 0 takes the scalar
+  // head, the last block the scalar tail.
+  const Split4 sp = split4(keys, n);
+  const int64_t per = (sp.nvec + gridDim.x - 1) / gridDim.x;
+  const int64_t vb = (int64_t)blockIdx.x * per < sp.nvec ? (int64_t)blockIdx.x * per : sp.nvec;
+  const int64_t ve = vb + per < sp.nvec ? vb + per : sp.nvec;
+  {  // scalar head (block 0, lanes 0-2) and tail (last block, lanes 64-66)
+    int64_t i = -1;
+    if (blockIdx.x == 0 && threadIdx.x < sp.head) i = threadIdx.x;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x >= 64 && threadIdx.x - 64 < n - sp.tail)
+      i = sp.tail + threadIdx.x - 64;
+    join_split_one(c, o, hot, tclamp, i >= 0, i >= 0 ? (uint32_t)keys[i] : 0u);
+  }
+
+  const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
+  const int64_t tile_vecs = (int64_t)kJoinThreads * kJoinVecs;
+  const int64_t full_end = vb + ((ve - vb) / tile_vecs) * tile_vecs;
+  const bool all_valid[kJoinVecs] = {true, true, true, true};
+  auto load_tile = [&](i32x4(&x)[kJoinVecs], int64_t base) {
+    const i32x4 *p = vk + base + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kJoinVecs; ++u) x[u] = load_stream4(p + u * kJoinThreads);
+  };
+  i32x4 xa[kJoinVecs], xb[kJoinVecs];
+  int64_t base = vb;
+  if (base < full_end) load_tile(xa, base);
+  while (base < full_end) {
+    int64_t nxt = base + tile_vecs;
+    load_tile(xb, nxt < full_end ? nxt : base);
+    join_split_batch<GROUPS, kJoinVecs, false>(c, o, hot, tclamp, xa, all_valid);
+    base = nxt;
+    if (base >= full_end) break;
+    nxt = base + tile_vecs;
+    load_tile(xa, nxt < full_end ? nxt : base);
+    join_split_batch<GROUPS, kJoinVecs, false>(c, o, hot, tclamp, xb, all_valid);
+    base = nxt;
+  }
+  if (full_end < ve) {  // last partial tile
+    i32x4 x[kJoinVecs];
+    bool valid[kJoinVecs];
+#pragma unroll
+    for (int u = 0; u < kJoinVecs; ++u) {
+      const int64_t vi = full_end + u * kJoinThreads + threadIdx.x;
+      valid[u] = vi < ve;
+      x[u] = valid[u] ? load_stream4(vk + vi) : i32x4{0, 0, 0, 0};
+    }
+    join_split_batch<GROUPS, kJoinVecs, true>(c, o, hot, tclamp, x, valid);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) seg_count[blockIdx.x] = *lcount < seg_cap ? *lcount : (uint32_t)seg_cap;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) hist[(int64_t)p * gridDim.x + blockIdx.x] = lhist[p];
+  join_flush(c, flag);
+}
+
+// ---------------------------------------------------------------------------
+// Partitioned form, pass 3: units of slice-ordered cold keys.  Workgroup b
+// takes a contiguous range of units, so consecutive units usually share a
+// slice and the slice is copied into LDS once.  Slices with few keys are
+// gathered from global memory instead.
+// ---------------------------------------------------------------------------
+constexpr int kSliceUnroll = 16;
+
+// One unit of slice-ordered cold keys: DENSE reads the LDS copy of the slice,
+// otherwise the words are gathered from global memory.
+template <int GROUPS, bool DENSE>
+__device__ __forceinline__ void join_unit(JoinCtx<GROUPS> &c, const int32_t *__restrict__ items, uint32_t lo,
+                                          uint32_t hi, const uint32_t *slice, int32_t sbase, uint32_t smax,
+                                          rsrc_t wr) {
+  auto lookup = [&](int32_t k) -> uint32_t {
+    if (DENSE) {
+      const uint32_t local = (uint32_t)(k - sbase);
+      return slice[local < smax ? local : smax];
+    }
+    return buffer_load_record(wr, k, 0, 0, 0);
+  };
+  // Chunks of kSliceUnroll keys per lane; the next chunk is loaded while the
+  // current one is looked up.
+  constexpr uint32_t kChunk = kSliceUnroll * kJoinThreads;
+  uint32_t i = lo + threadIdx.x;
+  const uint32_t full = lo + ((hi - lo) / kChunk) * kChunk;
+  int32_t k[kSliceUnroll], kn[kSliceUnroll];
+  auto load = [&](int32_t(&kk)[kSliceUnroll], uint32_t at) {
+#pragma unroll
+    for (int j = 0; j < kSliceUnroll; ++j) kk[j] = load_stream1(items + at + j * kJoinThreads);
+  };
+  if (i < full) load(k, i);
+  for (; i < full; i += kChunk) {
+    load(kn, i + kChunk < full ? i + kChunk : i);
+    uint32_t w[kSliceUnroll];
+#pragma unroll
+    for (int j = 0; j < kSliceUnroll; ++j) w[j] = lookup(k[j]);
+    uint32_t all = kValid;
+#pragma unroll
+    for (int j = 0; j < kSliceUnroll; ++j) {
+      all &= w[j];
+      join_add(c, w[j]);
+    }
+    if (__builtin_expect(!(all & kValid), 0)) {
+#pragma unroll
+      for (int j = 0; j < kSliceUnroll; ++j)
+        if (!w[j]) join_slow(c, (uint32_t)k[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kSliceUnroll; ++j) k[j] = kn[j];
+  }
+  for (; i < hi; i += kJoinThreads) {
+    const int32_t k = load_stream1(items + i);
+    const uint32_t w = lookup(k);
+    join_add(c, w);
+    if (!w) join_slow(c, (uint32_t)k);
+  }
+}
+
+template <int GROUPS>
+__global__ __launch_bounds__(kJoinThreads) void join_slice_kernel(
+    const int32_t *__restrict__ items, const uint32_t *__restrict__ slice_off, const uint32_t *__restrict__ unit_start,
+    int32_t P, const uint32_t *__restrict__ words, int32_t n_rows, int32_t t, int32_t wshift,
+    const int32_t *__restrict__ price, const int8_t *__restrict__ cat, int32_t cat_lt, int64_t *__restrict__ out_sum,
+    int64_t *__restrict__ out_cnt, int32_t *flag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int kBinBytes = GROUPS == 16 ? kJoinBins * kWave * 8 : 0;
+  JoinCtx<GROUPS> c;
+  join_init(c, smem, price, cat, cat_lt, n_rows, out_sum, out_cnt);
+  const int32_t W = 1 << wshift;
+  uint32_t *slice = reinterpret_cast<uint32_t *>(smem + kBinBytes);
+  uint32_t *ustart = slice + W;
+  uint32_t *soff = ustart + (P + 1);
+  for (int p = threadIdx.x; p <= P; p += blockDim.x) {
+    ustart[p] = unit_start[p];
+    soff[p] = slice_off[p];
+  }
+  __syncthreads();
+  const rsrc_t wr = record_buffer(words, (uint32_t)n_rows);
+  const uint32_t units = ustart[P];
+  const uint32_t u0 = (uint32_t)((uint64_t)units * blockIdx.x / gridDim.x);
+  const uint32_t u1 = (uint32_t)((uint64_t)units * (blockIdx.x + 1) / gridDim.x);
+  int32_t p = 0;
+  int32_t loaded = -1;
+  for (uint32_t u = u0; u < u1; ++u) {
+    while (p + 1 < P && ustart[p + 1] <= u) ++p;
+    const uint32_t lo = soff[p] + (u - ustart[p]) * kUnitItems;
+    const uint32_t hi = lo + kUnitItems < soff[p + 1] ? lo + kUnitItems : soff[p + 1];
+    const int64_t sbase = (int64_t)t + ((int64_t)p << wshift);
+    const int32_t slen = (int32_t)((int64_t)n_rows - sbase < W ? (int64_t)n_rows - sbase : W);
+    const bool dense = (soff[p + 1] - soff[p]) >= (uint32_t)(W >> 3);
+    if (dense && loaded != p) {
+      __syncthreads();
+      stage_words(slice, words, sbase, slen);
+      __syncthreads();
+      loaded = p;
+    }
+    if (dense) join_unit<GROUPS, true>(c, items, lo, hi, slice, (int32_t)sbase, (uint32_t)slen - 1, wr);
+    else join_unit<GROUPS, false>(c, items, lo, hi, slice, (int32_t)sbase, (uint32_t)slen - 1, wr);
+  }
+  join_flush(c, flag);
+}
+
+int grid_1d(int64_t n, int threads, int cap) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g > cap) g = cap;
+  return g < 1 ? 1 : (int)g;
+}
+
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 48 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Capacities and launchers
+// ---------------------------------------------------------------------------
+size_t join_lds_bytes(int groups, int32_t hot_rows) {
+  const size_t hot = (((size_t)(hot_rows > 0 ? hot_rows : 0) + 4) & ~(size_t)3) * 4;
+  return (groups == 16 ? (size_t)kJoinBins * kWave * 8 : 0) + hot;
+}
+
+int32_t join_max_hot_rows(int groups, const DeviceInfo &dev) {
+  // bins + static reduction scratch + slice histogram of the partitioned form
+  const size_t fixed = join_lds_bytes(groups, 0) - 16 + 256 + (size_t)(kMaxSlices + 4) * 4;
+  if (dev.lds_per_block <= fixed) return 0;
+  return (int32_t)(((dev.lds_per_block - fixed) / 4) & ~(size_t)3) - 4;
+}
+
+JoinPlan join_plan(int64_t n_fact, int32_t n_rows, int32_t t, int groups, const DeviceInfo &dev) {
+  JoinPlan pl;
+  pl.blocks = dev.cu_count > 0 ? dev.cu_count : 256;
+  pl.wshift = kJoinSliceShift;
+  const int64_t cold_rows = (int64_t)n_rows - t;
+  pl.slices = cold_rows > 0 ? (int32_t)((cold_rows + (1 << pl.wshift) - 1) >> pl.wshift) : 0;
+  pl.round = n_fact < kMaxRound ? n_fact : kMaxRound;
+  const int64_t nvec = (pl.round + 3) / 4 + 1;
+  pl.seg_cap = 4 * ((nvec + pl.blocks - 1) / pl.blocks) + 8;
+  (void)groups;
+  return pl;
+}
+
+size_t join_partition_bytes(const JoinPlan &pl) {
+  auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const int32_t P = pl.slices > 0 ? pl.slices : 1;
+  return r((size_t)pl.blocks * pl.seg_cap * 4)       // cold segments
+         + r((size_t)pl.round * 4 + 16)              // slice-ordered keys
+         + r((size_t)P * pl.blocks * 4)              // (slice, block) counts
+         + r((size_t)P * 4) + r(4) + r((size_t)pl.blocks * 4) + 2 * r((size_t)(P + 1) * 4);
+}
+
+hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price, const int8_t *cat, int32_t n_rows,
+                       int32_t cat_lt, int32_t by_cat, int32_t hot_rows, int64_t *out_sum, int64_t *out_cnt,
+                       uint32_t *words, int32_t *flag, void *part_ws, size_t part_bytes, const DeviceInfo &dev,
+                       hipStream_t s) {
+  const int groups = by_cat ? 16 : 1;
+  StageTimer st = stage_begin("join_pack", s);
+  hipLaunchKernelGGL(join_pack_kernel, dim3(grid_1d(n_rows > 16 ? n_rows : 16, 256, dev.cu_count * 16)), dim3(256), 0,
+                     s, price, cat, n_rows, cat_lt, by_cat, words, out_sum, out_cnt, flag);
+  hipError_t e = hipGetLastError();
+  stage_end(st, s);
+  if (e != hipSuccess || n_fact == 0) return e;
+  int32_t t = hot_rows;
+  const int32_t cap = join_max_hot_rows(groups, dev);
+  if (t > cap) t = cap;
+  if (t > n_rows) t = n_rows;
+  if (t < 0) t = 0;
+
+  const JoinPlan pl = join_plan(n_fact, n_rows, t, groups, dev);
+  const bool partitioned = part_ws && n_fact >= kPartitionMinFact && pl.slices > 0 && pl.slices <= kMaxSlices &&
+                           part_bytes >= join_partition_bytes(pl);
+  if (!partitioned) {
+    const size_t lds = join_lds_bytes(groups, t);
+    // Every lane's bins must see fewer than 2^19 rows per launch: at most 16
+    // waves share a bin, so a thread handles at most 2^14 rows per launch.
+    const int64_t per_launch_max = (int64_t)dev.cu_count * kJoinThreads * (1LL << 14);
+    if (groups == 16) allow_lds(join_kernel<16>, lds);
+    else allow_lds(join_kernel<1>, lds);
+    for (int64_t off = 0; off < n_fact; off += per_launch_max) {
+      const int64_t n = n_fact - off < per_launch_max ? n_fact - off : per_launch_max;
+      const int64_t need = (n + 4LL * kJoinThreads - 1) / (4LL * kJoinThreads);
+      const int grid = need < dev.cu_count ? (int)need : dev.cu_count;
+      st = stage_begin("join_single_pass", s);
+      if (groups == 16)
+        hipLaunchKernelGGL(join_kernel<16>, dim3(grid), dim3(kJoinThreads), lds, s, keys + off, n, words, n_rows, t,
+                           price, cat, cat_lt, out_sum, out_cnt, flag);
+      else
+        hipLaunchKernelGGL(join_kernel<1>, dim3(grid), dim3(kJoinThreads), lds, s, keys + off, n, words, n_rows, t,
+                           price, cat, cat_lt, out_sum, out_cnt, flag);
+      e = hipGetLastError();
+      stage_end(st, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+
+  // Partitioned form, one round of at most pl.round rows at a time.
+  auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  char *ws = (char *)part_ws;
+  int32_t *seg = (int32_t *)ws;
+  ws += r((size_t)pl.blocks * pl.seg_cap * 4);
+  int32_t *items = (int32_t *)ws;
+  ws += r((size_t)pl.round * 4 + 16);
+  SliceTables tab;
+  tab.hist = (uint32_t *)ws;
+  ws += r((size_t)pl.slices * pl.blocks * 4);
+  tab.row_total = (uint32_t *)ws;
+  ws += r((size_t)pl.slices * 4);
+  tab.total = (uint32_t *)ws;
+  ws += r(4);
+  tab.seg_count = (uint32_t *)ws;
+  ws += r((size_t)pl.blocks * 4);
+  tab.slice_off = (uint32_t *)ws;
+  ws += r((size_t)(pl.slices + 1) * 4);
+  tab.unit_start = (uint32_t *)ws;
+
+  const size_t lds1 = join_lds_bytes(groups, t) + (size_t)(pl.slices + 4) * 4;
+  const size_t lds3 = (groups == 16 ? (size_t)kJoinBins * kWave * 8 : 0) + ((size_t)4 << pl.wshift) +
+                      (size_t)2 * (pl.slices + 1) * 4;
+  if (groups == 16) {
+    allow_lds(join_split_kernel<16>, lds1);
+    allow_lds(join_slice_kernel<16>, lds3);
+  } else {
+    allow_lds(join_split_kernel<1>, lds1);
+    allow_lds(join_slice_kernel<1>, lds3);
+  }
+  for (int64_t off = 0; off < n_fact; off += pl.round) {
+    const int64_t n = n_fact - off < pl.round ? n_fact - off : pl.round;
+    st = stage_begin("join_split", s);
+    if (groups == 16)
+      hipLaunchKernelGGL(join_split_kernel<16>, dim3(pl.blocks), dim3(kJoinThreads), lds1, s, keys + off, n, words,
+                         n_rows, t, pl.slices, pl.wshift, price, cat, cat_lt, out_sum, out_cnt, flag, seg, pl.seg_cap,
+                         tab.seg_count, tab.hist);
+    else
+      hipLaunchKernelGGL(join_split_kernel<1>, dim3(pl.blocks), dim3(kJoinThreads), lds1, s, keys + off, n, words,
+                         n_rows, t, pl.slices, pl.wshift, price, cat, cat_lt, out_sum, out_cnt, flag, seg, pl.seg_cap,
+                         tab.seg_count, tab.hist);
+    e = hipGetLastError();
+    stage_end(st, s);
+    st = stage_begin("join_plan", s);
+    if (e == hipSuccess) e = launch_partition_plan(tab, pl.slices, pl.blocks, s);
+    stage_end(st, s);
+    st = stage_begin("join_scatter", s);
+    if (e == hipSuccess)
+      e = launch_partition_scatter(tab, pl.slices, pl.blocks, seg, nullptr, pl.seg_cap, t, pl.wshift, items, nullptr,
+                                   s);
+    stage_end(st, s);
+    if (e != hipSuccess) return e;
+    st = stage_begin("join_slice", s);
+    if (groups == 16)
+      hipLaunchKernelGGL(join_slice_kernel<16>, dim3(pl.blocks), dim3(kJoinThreads), lds3, s, items, tab.slice_off,
+                         tab.unit_start, pl.slices, words, n_rows, t, pl.wshift, price, cat, cat_lt, out_sum, out_cnt,
+                         flag);
+    else
+      hipLaunchKernelGGL(join_slice_kernel<1>, dim3(pl.blocks), dim3(kJoinThreads), lds3, s, items, tab.slice_off,
+                         tab.unit_start, pl.slices, words, n_rows, t, pl.wshift, price, cat, cat_lt, out_sum, out_cnt,
+                         flag);
+    e = hipGetLastError();
+    stage_end(st, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace skew

@@ -31,22 +31,52 @@ hipError_t launch_permute_dims(const int32_t *perm, int32_t n, const int32_t *pr
 hipError_t launch_recode(const int32_t *keys, int64_t n, const int32_t *rank, int32_t n_keys, int32_t *out,
                          const DeviceInfo &dev, hipStream_t s);
 
+// ---- prefix sums and cold-item partitioning ----
+struct SliceTables;
+hipError_t launch_exclusive_scan(uint32_t *a, int64_t n, uint32_t *total, hipStream_t s);
+// Scan of the (slice, block) counts and the slice/unit tables.
+hipError_t launch_partition_plan(const SliceTables &tab, int32_t P, int32_t B, hipStream_t s);
+// Move every block's cold items into slice order.
+hipError_t launch_partition_scatter(const SliceTables &tab, int32_t P, int32_t B, const int32_t *seg_keys,
+                                    const int32_t *seg_vals, int64_t seg_cap, int32_t t, int32_t wshift,
+                                    int32_t *out_keys, int32_t *out_vals, hipStream_t s);
+
 // ---- queries (Section 4) ----
 constexpr int kJoinThreads = 1024;
 constexpr int kGroupThreads = 1024;
-constexpr int kGroupCopies = 16;  // hottest ranks kept as per-lane copies (Section 4.2.2)
+constexpr int kGroupCopies = 16;        // hottest ranks kept as per-lane copies (Section 4.2.2)
+constexpr int kJoinSliceShift = 15;     // 32768 dimension words per LDS slice
+constexpr int kGroupSliceShift = 13;    // 8192 groups per LDS slice
+constexpr int64_t kMaxRound = 1LL << 28;         // rows per round of the partitioned form
+constexpr int64_t kPartitionMinFact = 1LL << 22;  // below this the single pass is used
+
+// Partitioned form: cold items of each round go through per-block segments,
+// a (slice, block) histogram, a scatter into slice order and a slice pass.
+struct JoinPlan {
+  int32_t blocks, wshift, slices;
+  int64_t round, seg_cap;
+};
+using GroupPlan = JoinPlan;
+
 size_t join_lds_bytes(int groups, int32_t hot_rows);
 int32_t join_max_hot_rows(int groups, const DeviceInfo &dev);
+JoinPlan join_plan(int64_t n_fact, int32_t n_rows, int32_t t, int groups, const DeviceInfo &dev);
+size_t join_partition_bytes(const JoinPlan &pl);
 size_t group_lds_bytes(int32_t hot_groups);
 int32_t group_max_hot_groups(const DeviceInfo &dev);
+GroupPlan group_plan(int64_t n_fact, int32_t n_groups, int32_t t, const DeviceInfo &dev);
+size_t group_partition_bytes(const GroupPlan &pl);
 
+// part_ws/part_bytes: optional workspace for the partitioned form (NULL: single pass).
 hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price, const int8_t *cat, int32_t n_rows,
                        int32_t cat_lt, int32_t by_cat, int32_t hot_rows, int64_t *out_sum, int64_t *out_cnt,
-                       uint32_t *words, int32_t *flag, const DeviceInfo &dev, hipStream_t s);
+                       uint32_t *words, int32_t *flag, void *part_ws, size_t part_bytes, const DeviceInfo &dev,
+                       hipStream_t s);
 
 enum GroupMode { kGroupRange = 0, kGroupHash = 1, kGroupAtomic = 2 };
 hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact, int32_t n_groups, GroupMode mode,
                         int32_t hot_groups, const int32_t *perm, int64_t *out_sum, int64_t *out_cnt,
-                        uint64_t *acc_sum, uint64_t *acc_cnt, int32_t *flag, const DeviceInfo &dev, hipStream_t s);
+                        uint64_t *acc_sum, uint64_t *acc_cnt, int32_t *flag, void *part_ws, size_t part_bytes,
+                        const DeviceInfo &dev, hipStream_t s);
 
 }  // namespace skew

@@ -117,7 +117,6 @@ __global__ __launch_bounds__(kHistThreads) void histogram_kernel(const int32_t *
 // ---------------------------------------------------------------------------
 constexpr int kSortThreads = 256;
 constexpr int kSortRounds = kSortTile / kSortThreads;  // 16
-constexpr int kScanThreads = 1024;
 
 // Lanes of this wave holding the same 8-bit digit (restricted to `active`).
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
@@ -155,32 +154,6 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
   }
   __syncthreads();
   hist[(int64_t)tid * tiles + blockIdx.x] = h[tid];
-}
-
-// Exclusive scan of `total` u32 entries in place, one workgroup: every thread
-// owns a contiguous segment.
-__global__ __launch_bounds__(kScanThreads) void exclusive_scan_kernel(uint32_t *__restrict__ a, int64_t total) {
-  __shared__ uint32_t part[kScanThreads];
-  const int tid = threadIdx.x;
-  const int64_t seg = (total + kScanThreads - 1) / kScanThreads;
-  const int64_t lo = (int64_t)tid * seg;
-  const int64_t hi = lo + seg < total ? lo + seg : total;
-  uint32_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += a[i];
-  part[tid] = s;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {  // Hillis-Steele inclusive scan
-    const uint32_t add = tid >= off ? part[tid - off] : 0u;
-    __syncthreads();
-    part[tid] += add;
-    __syncthreads();
-  }
-  uint32_t run = tid ? part[tid - 1] : 0u;
-  for (int64_t i = lo; i < hi; ++i) {
-    const uint32_t x = a[i];
-    a[i] = run;
-    run += x;
-  }
 }
 
 template <bool FIRST, bool LAST>
@@ -343,7 +316,8 @@ hipError_t launch_rank_sort(const uint32_t *counts_by_key, int32_t n_keys, int64
     else
       hipLaunchKernelGGL(radix_upsweep_kernel<false>, dim3(tiles), dim3(kSortThreads), 0, s, kin, n_keys, shift, maxv,
                          digit_hist, tiles);
-    hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, digit_hist, total);
+    hipError_t se = launch_exclusive_scan(digit_hist, total, nullptr, s);
+    if (se != hipSuccess) return se;
     if (first && last)
       hipLaunchKernelGGL((radix_downsweep_kernel<true, true>), dim3(tiles), dim3(kSortThreads), 0, s, kin, vin, n_keys,
                          shift, maxv, digit_hist, tiles, kout, vout);

@@ -13,6 +13,10 @@
 #include "../../include/skew.h"
 #include "device_common.h"
 #include "kernels.h"
+#include "profiler.h"
+#include "query_common.h"
+
+#include <vector>
 
 namespace {
 
@@ -100,9 +104,39 @@ BuildWs build_ws(int32_t n_keys) {
   return w;
 }
 
+// Workgroups of the partitioned form (segments are sized for this many).
+constexpr int kPartBlocks = 256;
+
+skew::DeviceInfo sizing_device() {
+  skew::DeviceInfo d;
+  d.cu_count = kPartBlocks;
+  return d;
+}
+
 size_t join_ws(int32_t n_rows) { return skew::kFlagBytes + round_up((size_t)n_rows * 4); }
 
+// Extra bytes for the partitioned join (0 when it would not be used).
+size_t join_part_ws(int64_t n_fact, int32_t n_rows) {
+  if (n_fact < skew::kPartitionMinFact) return 0;
+  const skew::JoinPlan pl = skew::join_plan(n_fact, n_rows, 0, 16, sizing_device());
+  if (pl.slices <= 0 || pl.slices > skew::kMaxSlices) return 0;
+  return round_up(skew::join_partition_bytes(pl));
+}
+
 size_t group_ws(int32_t n_groups) { return skew::kFlagBytes + 2 * round_up((size_t)n_groups * 8); }
+
+size_t group_part_ws(int64_t n_fact, int32_t n_groups) {
+  if (n_fact < skew::kPartitionMinFact) return 0;
+  const skew::GroupPlan pl = skew::group_plan(n_fact, n_groups, 0, sizing_device());
+  if (pl.slices <= 0 || pl.slices > skew::kMaxSlices) return 0;
+  return round_up(skew::group_partition_bytes(pl));
+}
+
+skew::DeviceInfo part_device(const skew::DeviceInfo &dev) {
+  skew::DeviceInfo d = dev;
+  if (d.cu_count > kPartBlocks) d.cu_count = kPartBlocks;
+  return d;
+}
 
 int read_flag(const void *workspace, hipStream_t s) {
   int32_t flag = 0;
@@ -114,6 +148,43 @@ int read_flag(const void *workspace, hipStream_t s) {
 
 }  // namespace
 
+
+// ---------------------------------------------------------------------------
+// Stage timing: while enabled, every launch stage records a pair of HIP events
+// on the stream it runs on; skew_profile_report resolves them.
+// ---------------------------------------------------------------------------
+namespace {
+struct StageRecord {
+  const char *name;
+  hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<StageRecord> g_prof;
+}  // namespace
+
+namespace skew {
+
+StageTimer stage_begin(const char *name, hipStream_t s) {
+  StageTimer t;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return t;
+  StageRecord r{name, nullptr, nullptr};
+  if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return t;
+  if (hipEventRecord(r.start, s) != hipSuccess) return t;
+  g_prof.push_back(r);
+  t.slot = (int)g_prof.size() - 1;
+  return t;
+}
+
+void stage_end(const StageTimer &t, hipStream_t s) {
+  if (t.slot < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (t.slot < (int)g_prof.size()) (void)hipEventRecord(g_prof[t.slot].stop, s);
+}
+
+}  // namespace skew
+
 extern "C" {
 
 const char *skew_last_error(void) { return g_last_error.c_str(); }
@@ -124,8 +195,12 @@ size_t skew_workspace_bytes(int op, int64_t n_fact, int32_t n_keys) {
     case SKEW_OP_BUILD:
       return build_ws(n_keys).total;
     case SKEW_OP_JOIN:
-      return join_ws(n_keys);
+      return join_ws(n_keys) + join_part_ws(n_fact, n_keys);
     case SKEW_OP_GROUP:
+      return group_ws(n_keys) + group_part_ws(n_fact, n_keys);
+    case SKEW_OP_JOIN_SINGLE_PASS:
+      return join_ws(n_keys);
+    case SKEW_OP_GROUP_SINGLE_PASS:
       return group_ws(n_keys);
     default:
       return 0;
@@ -161,9 +236,11 @@ int build_skew_layout(const int32_t *fact_keys, int64_t n_fact, int32_t n_keys, 
   uint32_t *counts = (uint32_t *)(ws + w.counts);
 
   // 1. key histogram (aggregation Q3), then wait once to validate the keys.
+  skew::StageTimer st = skew::stage_begin("build_histogram", s);
   hipError_t e = skew::launch_fill_u32((uint32_t *)flag, 1, 0u, s);
   if (e == hipSuccess) e = skew::launch_fill_u32(counts, n_keys, 0u, s);
   if (e == hipSuccess) e = skew::launch_histogram(fact_keys, n_fact, n_keys, counts, flag, dev, s);
+  skew::stage_end(st, s);
   if (e != hipSuccess) return hip_fail(e, "histogram launch");
   int32_t bad = 0;
   e = hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, s);
@@ -172,12 +249,20 @@ int build_skew_layout(const int32_t *fact_keys, int64_t n_fact, int32_t n_keys, 
   if (bad) return fail(SKEW_ERANGE, "a fact key lies outside [0, %d)", n_keys);
 
   // 2. sort keys by frequency, 3. invert, 4. copy the dimension, 5. recode the facts.
+  st = skew::stage_begin("build_rank_sort", s);
   e = skew::launch_rank_sort(counts, n_keys, n_fact, perm, counts_by_rank, (uint32_t *)(ws + w.keys_a),
                              (uint32_t *)(ws + w.keys_b), (int32_t *)(ws + w.vals_a), (int32_t *)(ws + w.vals_b),
                              (uint32_t *)(ws + w.hist), s);
+  skew::stage_end(st, s);
+  st = skew::stage_begin("build_inverse", s);
   if (e == hipSuccess) e = skew::launch_inverse(perm, n_keys, rank, s);
+  skew::stage_end(st, s);
+  st = skew::stage_begin("build_permute_dims", s);
   if (e == hipSuccess) e = skew::launch_permute_dims(perm, n_keys, dim_price, dim_category, price_out, category_out, s);
+  skew::stage_end(st, s);
+  st = skew::stage_begin("build_recode", s);
   if (e == hipSuccess && fact_recoded) e = skew::launch_recode(fact_keys, n_fact, rank, n_keys, fact_recoded, dev, s);
+  skew::stage_end(st, s);
   if (e != hipSuccess) return hip_fail(e, "layout launch");
   return ok();
 }
@@ -208,9 +293,11 @@ int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *d
   const int32_t t = hot_rows == SKEW_HOT_AUTO ? skew::join_max_hot_rows(groups, dev) : hot_rows;
   const hipStream_t s = (hipStream_t)stream;
   char *ws = (char *)workspace;
+  void *part = workspace_bytes > need ? (void *)(ws + need) : nullptr;
   const hipError_t e = skew::launch_join(fact_keys, n_fact, dim_price, dim_category, n_rows, cat_lt,
                                          group_by_category, t, out_sum, out_count,
-                                         (uint32_t *)(ws + skew::kFlagBytes), (int32_t *)ws, dev, s);
+                                         (uint32_t *)(ws + skew::kFlagBytes), (int32_t *)ws, part,
+                                         part ? workspace_bytes - need : 0, part_device(dev), s);
   if (e != hipSuccess) return hip_fail(e, "join launch");
   if (check_enabled()) return read_flag(workspace, s);
   return ok();
@@ -249,9 +336,11 @@ int group_aggregate(const int32_t *group_keys, const int32_t *values, int64_t n_
   const hipStream_t s = (hipStream_t)stream;
   char *ws = (char *)workspace;
   const size_t acc = round_up((size_t)n_groups * 8);
+  void *part = workspace_bytes > need ? (void *)(ws + need) : nullptr;
   const hipError_t e = skew::launch_group(group_keys, values, n_fact, n_groups, mode, t, perm, out_sum, out_count,
                                           (uint64_t *)(ws + skew::kFlagBytes),
-                                          (uint64_t *)(ws + skew::kFlagBytes + acc), (int32_t *)ws, dev, s);
+                                          (uint64_t *)(ws + skew::kFlagBytes + acc), (int32_t *)ws, part,
+                                          part ? workspace_bytes - need : 0, part_device(dev), s);
   if (e != hipSuccess) return hip_fail(e, "group launch");
   if (check_enabled()) return read_flag(workspace, s);
   return ok();
@@ -260,6 +349,50 @@ int group_aggregate(const int32_t *group_keys, const int32_t *values, int64_t n_
 int skew_query_status(const void *workspace, size_t workspace_bytes, void *stream) {
   if (!workspace || workspace_bytes < skew::kFlagBytes) return fail(SKEW_EINVAL, "workspace is NULL or too small");
   return read_flag(workspace, (hipStream_t)stream);
+}
+
+void skew_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+}
+
+int skew_profile_report(char *names, int names_bytes, float *ms, int *calls, int max_stages) {
+  std::vector<StageRecord> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recs.swap(g_prof);
+  }
+  std::vector<std::string> keys;
+  std::vector<float> tot;
+  std::vector<int> cnt;
+  for (auto &r : recs) {
+    float v = 0.f;
+    if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&v, r.start, r.stop) == hipSuccess) {
+      size_t i = 0;
+      while (i < keys.size() && keys[i] != r.name) ++i;
+      if (i == keys.size()) {
+        keys.emplace_back(r.name);
+        tot.push_back(0.f);
+        cnt.push_back(0);
+      }
+      tot[i] += v;
+      cnt[i] += 1;
+    }
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  const int n = (int)keys.size() < max_stages ? (int)keys.size() : max_stages;
+  int off = 0;
+  for (int i = 0; i < n; ++i) {
+    if (ms) ms[i] = tot[i];
+    if (calls) calls[i] = cnt[i];
+    if (names && off + (int)keys[i].size() + 1 < names_bytes) {
+      std::memcpy(names + off, keys[i].c_str(), keys[i].size() + 1);
+      off += (int)keys[i].size() + 1;
+    }
+  }
+  if (names && off < names_bytes) names[off] = 0;
+  return n;
 }
 
 int32_t skew_max_hot_rows(int32_t group_by_category) {

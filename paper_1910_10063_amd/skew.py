@@ -26,12 +26,15 @@ SKEW_EDEVICE = -5
 SKEW_OP_BUILD = 1
 SKEW_OP_JOIN = 2
 SKEW_OP_GROUP = 3
+SKEW_OP_JOIN_SINGLE_PASS = 4
+SKEW_OP_GROUP_SINGLE_PASS = 5
 
 SKEW_HOT_AUTO = -1
 SKEW_HOT_NONE = -2
 
 EXPORTED = ("skew_last_error", "skew_workspace_bytes", "build_skew_layout", "fk_join_aggregate", "group_aggregate",
-            "skew_query_status", "skew_max_hot_rows", "skew_max_hot_groups")
+            "skew_query_status", "skew_profile_enable", "skew_profile_report", "skew_max_hot_rows",
+            "skew_max_hot_groups")
 
 
 class SkewError(RuntimeError):
@@ -68,6 +71,10 @@ def load_library(path: str = LIB_PATH):
     lib.skew_max_hot_rows.restype = I32
     lib.skew_max_hot_groups.argtypes = []
     lib.skew_max_hot_groups.restype = I32
+    lib.skew_profile_enable.argtypes = [ctypes.c_int]
+    lib.skew_profile_enable.restype = None
+    lib.skew_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_int, P, P, ctypes.c_int]
+    lib.skew_profile_report.restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
     return lib
@@ -215,3 +222,20 @@ def max_hot_groups() -> int:
     if v < 0:
         _check(v)
     return int(v)
+
+
+def profile_enable(on: bool = True) -> None:
+    """Record HIP events around every launch stage from now on (see skew_profile_report)."""
+    load_library().skew_profile_enable(1 if on else 0)
+
+
+def profile_report(max_stages: int = 64) -> dict:
+    """{stage: (total_ms, launches)} of the stages recorded since the last report."""
+    lib = load_library()
+    names = ctypes.create_string_buffer(64 * max_stages)
+    ms = (ctypes.c_float * max_stages)()
+    calls = (ctypes.c_int * max_stages)()
+    n = lib.skew_profile_report(names, len(names), ctypes.cast(ms, ctypes.c_void_p),
+                                ctypes.cast(calls, ctypes.c_void_p), max_stages)
+    keys = names.raw.split(b"\0")[:n]
+    return {k.decode(): (float(ms[i]), int(calls[i])) for i, k in enumerate(keys)}

@@ -107,11 +107,16 @@ def test_join_by_category_reduced(s):
     d = {n: to_dev(h[n]) for n in ("fact", "price", "category")}
     L = skew.build_skew_layout(d["fact"], N, d["price"], d["category"])
     check_layout(L, ref)
-    for t in (0, 4096, 32768, skew.SKEW_HOT_AUTO):
-        s_, c_ = skew.fk_join_aggregate(L.fact_recoded, L.price, L.category, 16, True, hot_rows=t)
-        assert (host(s_) == es).all() and (host(c_) == ec).all(), ("skew", t)
-    s_, c_ = skew.fk_join_aggregate(d["fact"], d["price"], d["category"], 16, True, hot_rows=0)
-    assert (host(s_) == es).all() and (host(c_) == ec).all(), "identity"
+    for op in (skew.SKEW_OP_JOIN, skew.SKEW_OP_JOIN_SINGLE_PASS):  # partitioned and single-pass forms
+        ws = skew.workspace(op, F, N, DEV)
+        for t in (0, 4096, 32768, skew.SKEW_HOT_AUTO):
+            s_, c_ = skew.fk_join_aggregate(L.fact_recoded, L.price, L.category, 16, True, hot_rows=t, ws=ws)
+            assert (host(s_) == es).all() and (host(c_) == ec).all(), ("skew", op, t)
+        s_, c_ = skew.fk_join_aggregate(d["fact"], d["price"], d["category"], 16, True, hot_rows=0, ws=ws)
+        assert (host(s_) == es).all() and (host(c_) == ec).all(), ("identity", op)
+        s1, c1 = oracle.fk_join_aggregate(h["fact"], h["price"], h["category"], 4, False)
+        s_, c_ = skew.fk_join_aggregate(L.fact_recoded, L.price, L.category, 4, False, hot_rows=1000, ws=ws)
+        assert (host(s_) == s1).all() and (host(c_) == c1).all(), ("one group", op)
 
 
 # ---------------------------------------------------------------------------
@@ -135,24 +140,77 @@ def test_group_layout_matches_oracle(groups):
     check_layout(L, groups["ref"])
 
 
+GROUP_OPS = [skew.SKEW_OP_GROUP, skew.SKEW_OP_GROUP_SINGLE_PASS]
+
+
+@pytest.mark.parametrize("op", GROUP_OPS, ids=["partitioned", "single_pass"])
 @pytest.mark.parametrize("t", [1, 15, 16, 17, 64, 1024, 8192, 100_000, skew.SKEW_HOT_AUTO])
-def test_group_skew_every_t(groups, t):
-    say(f"group_aggregate skew t={t}")
-    ref, M = groups["ref"], groups["M"]
+def test_group_skew_every_t(groups, t, op):
+    say(f"group_aggregate skew t={t} op={op}")
+    ref, M, F = groups["ref"], groups["M"], groups["F"]
     keys = to_dev(ref.fact_recoded)
     vals = to_dev(groups["h"]["vals"])
     perm = to_dev(ref.perm)
-    s, c = skew.group_aggregate(keys, vals, M, hot_groups=t, perm=perm)
+    ws = skew.workspace(op, F, M, DEV)
+    s, c = skew.group_aggregate(keys, vals, M, hot_groups=t, perm=perm, ws=ws)
     assert (host(s) == groups["es"]).all() and (host(c) == groups["ec"]).all()
 
 
+@pytest.mark.parametrize("op", GROUP_OPS, ids=["partitioned", "single_pass"])
 @pytest.mark.parametrize("mode", [0, skew.SKEW_HOT_NONE, 4096])
-def test_group_identity_modes(groups, mode):
-    say(f"group_aggregate identity mode={mode}")
+def test_group_identity_modes(groups, mode, op):
+    say(f"group_aggregate identity mode={mode} op={op}")
     keys = to_dev(groups["h"]["keys"])
     vals = to_dev(groups["h"]["vals"])
-    s, c = skew.group_aggregate(keys, vals, groups["M"], hot_groups=mode)
+    ws = skew.workspace(op, groups["F"], groups["M"], DEV)
+    s, c = skew.group_aggregate(keys, vals, groups["M"], hot_groups=mode, ws=ws)
     assert (host(s) == groups["es"]).all() and (host(c) == groups["ec"]).all()
+
+
+@pytest.mark.parametrize("offset", [0, 1, 3])
+def test_partitioned_edges(offset):
+    """Partitioned forms on ragged/unaligned columns with escapes, negatives and bad keys."""
+    say(f"partitioned edges offset={offset}")
+    rng = np.random.default_rng(40 + offset)
+    N, F = 300_001, (1 << 22) + 12_345
+    price = rng.integers(1, 10001, N).astype(np.int32)
+    price[rng.integers(0, N, 50)] = rng.integers(-2**31, -1, 50)  # escapes, hot and cold
+    price[:3] = [-7, 2**30, 5]
+    cat = rng.integers(0, 16, N).astype(np.int8)
+    cat[rng.integers(0, N, 1000)] = -3
+    fact = (rng.zipf(1.2, F + offset) % N).astype(np.int32)
+    fd = to_dev(fact)[offset:]
+    for by_cat, cat_lt in ((True, 16), (False, 4)):
+        es, ec = oracle.fk_join_aggregate(fact[offset:], price, cat, cat_lt, by_cat)
+        ws = skew.workspace(skew.SKEW_OP_JOIN, F, N, DEV)
+        for t in (0, 7, 32768):
+            s, c = skew.fk_join_aggregate(fd, to_dev(price), to_dev(cat), cat_lt, by_cat, hot_rows=t, ws=ws)
+            assert (host(s) == es).all() and (host(c) == ec).all(), (by_cat, t)
+    # out-of-range keys in the partitioned join: skipped and flagged
+    bad = fact.copy()
+    bad[offset + 100] = N + 5
+    bad[offset + F // 2] = -1
+    ws = skew.workspace(skew.SKEW_OP_JOIN, F, N, DEV)
+    s, c = skew.fk_join_aggregate(to_dev(bad)[offset:], to_dev(price), to_dev(cat), 16, True, hot_rows=100, ws=ws)
+    es, ec = oracle.fk_join_aggregate(bad[offset:], price, cat, 16, True)
+    assert (host(s) == es).all() and (host(c) == ec).all()
+    with pytest.raises(skew.SkewError):
+        skew.query_status(ws)
+    # group-by: negative values, bad keys, keys and values misaligned to each other
+    M = 50_000
+    gk = (rng.zipf(1.1, F + 8) % (M + 3)).astype(np.int32)  # a few keys >= M
+    gv = rng.integers(-2**31, 2**31, F + 8, dtype=np.int64).astype(np.int32)
+    for voff in (offset, (offset + 2) % 4):
+        keys = to_dev(gk)[offset:offset + F]
+        vals = to_dev(gv)[voff:voff + F]
+        es, ec, inv = oracle.group_aggregate(gk[offset:offset + F], gv[voff:voff + F], M)
+        assert inv > 0
+        gws = skew.workspace(skew.SKEW_OP_GROUP, F, M, DEV)
+        for t in (0, 5, 16, 3000):
+            s, c = skew.group_aggregate(keys, vals, M, hot_groups=t, ws=gws)
+            assert (host(s) == es).all() and (host(c) == ec).all(), (voff, t)
+        with pytest.raises(skew.SkewError):
+            skew.query_status(gws)
 
 
 # ---------------------------------------------------------------------------
