@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1_000_000_000, help="fact rows the CPU oracle is timed on")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="headline query only (for profiler runs)")
+    ap.add_argument("--with-group", action="store_true", help="run the group-by workload even with --no-extras")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (reference for profiler byte counters)")
     args = ap.parse_args()
@@ -254,6 +255,7 @@ def main():
             del d, L
             torch.cuda.empty_cache()
         result["zipf_sweep"] = sweep_s
+    if not args.no_extras or args.with_group:
         result["group_by"] = bench_group_by(K, WU, dev, stream)
 
     if not args.no_cpu:

@@ -88,11 +88,12 @@ __device__ __forceinline__ void group_one(GroupCtx &c, int32_t g, int32_t v) {
   }
 }
 
-// LDS layout of the range mode: hot_sum[kCopySlots + t] | hot_cnt[kCopySlots + t].
-__device__ __forceinline__ void group_range_init(GroupCtx &c, unsigned char *smem, int32_t t) {
+// LDS layout of the range mode: hot_sum[kCopySlots + t + extra] |
+// hot_cnt[kCopySlots + t + extra]; the extra slots are never flushed.
+__device__ __forceinline__ void group_range_init(GroupCtx &c, unsigned char *smem, int32_t t, int32_t extra = 0) {
   c.hot_sum = reinterpret_cast<uint64_t *>(smem);
-  c.hot_cnt = reinterpret_cast<uint32_t *>(c.hot_sum + kCopySlots + t);
-  for (int i = threadIdx.x; i < kCopySlots + t; i += blockDim.x) {
+  c.hot_cnt = reinterpret_cast<uint32_t *>(c.hot_sum + kCopySlots + t + extra);
+  for (int i = threadIdx.x; i < kCopySlots + t + extra; i += blockDim.x) {
     c.hot_sum[i] = 0;
     c.hot_cnt[i] = 0;
   }
@@ -209,90 +210,60 @@ __global__ __launch_bounds__(kGroupThreads) void group_kernel(const int32_t *__r
 // (group, value) pair appended to this workgroup's segment of the cold
 // buffer and counted in its slice ((g - t) >> wshift).
 // ---------------------------------------------------------------------------
-struct PairSink {
-  int32_t *keys, *vals;  // this workgroup's segment
-  int64_t cap;
-  uint32_t *count;       // LDS
-  uint32_t *hist;        // LDS [P]
-  int32_t wshift;
+constexpr int kSplitVecs = 2;  // 16-byte vectors of keys (and of values) per lane per batch
+
+// Hot update without branches: lanes whose group is not hot add into a sink
+// slot of their own (kCopySlots + t + lane).
+__device__ __forceinline__ void group_hot_or_sink(const GroupCtx &c, bool h, uint32_t g, int32_t v, uint32_t sink) {
+  const uint32_t i = h ? (g < (uint32_t)c.ncopy ? g * kWave + lane_id() : kCopySlots + g) : sink;
+  lds_add_u64(&c.hot_sum[i], (uint64_t)(int64_t)v);
+  lds_add_u32(&c.hot_cnt[i], 1u);
+}
+
+struct PairSeg {
+  rsrc_t keys, vals;  // this workgroup's segment
 };
 
-__device__ __forceinline__ uint32_t wave_reserve(uint32_t *count, uint32_t n) {
-  uint32_t base = 0;
-  const uint64_t act = __ballot(1);
-  const int leader = __ffsll((unsigned long long)act) - 1;
-  if (lane_id() == leader) base = atomicAdd(count, n);
-  return __shfl(base, leader, kWave);
-}
-
-template <int V, bool GUARD>
-__device__ __forceinline__ void group_split_batch(GroupCtx &c, const PairSink &o, const i32x4 (&x)[V],
-                                                  const i32x4 (&y)[V], const bool (&valid)[V]) {
-  int32_t gk[V][4], gv[V][4];
+template <int V>
+__device__ __forceinline__ void group_split_batch(GroupCtx &c, const ColdSink &o, const PairSeg &seg,
+                                                  uint32_t hot_sink, const i32x4 (&x)[V], const i32x4 (&y)[V],
+                                                  const bool (&valid)[V]) {
+  uint32_t g[4 * V];
+  int32_t v[4 * V];
+  bool cold[4 * V];
 #pragma unroll
   for (int u = 0; u < V; ++u) {
-    gk[u][0] = x[u].x, gk[u][1] = x[u].y, gk[u][2] = x[u].z, gk[u][3] = x[u].w;
-    gv[u][0] = y[u].x, gv[u][1] = y[u].y, gv[u][2] = y[u].z, gv[u][3] = y[u].w;
+    g[4 * u] = (uint32_t)x[u].x, g[4 * u + 1] = (uint32_t)x[u].y;
+    g[4 * u + 2] = (uint32_t)x[u].z, g[4 * u + 3] = (uint32_t)x[u].w;
+    v[4 * u] = y[u].x, v[4 * u + 1] = y[u].y, v[4 * u + 2] = y[u].z, v[4 * u + 3] = y[u].w;
   }
-  bool cold[V][4];
 #pragma unroll
-  for (int u = 0; u < V; ++u)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int32_t g = gk[u][j];
-      const bool ok = !GUARD || valid[u];
-      const bool in = ok && (uint32_t)g < (uint32_t)c.m;
-      if (ok && !in) c.bad = true;
-      const bool h = in && g < c.t;
-      cold[u][j] = in && !h;
-      if (h) group_hot(c, g, gv[u][j]);
-    }
-  uint64_t mk[V][4];
-  uint32_t total = 0;
-#pragma unroll
-  for (int u = 0; u < V; ++u)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      mk[u][j] = __ballot(cold[u][j]);
-      total += (uint32_t)__popcll(mk[u][j]);
-    }
-  if (total == 0) return;
-  uint32_t pos = wave_reserve(o.count, total);
-  const uint64_t lt = (1ull << lane_id()) - 1ull;
-#pragma unroll
-  for (int u = 0; u < V; ++u)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (cold[u][j]) {
-        const uint32_t idx = pos + (uint32_t)__popcll(mk[u][j] & lt);
-        if (idx < o.cap) {
-          o.keys[idx] = gk[u][j];
-          o.vals[idx] = gv[u][j];
-        }
-        lds_add_u32(&o.hist[(uint32_t)(gk[u][j] - c.t) >> o.wshift], 1u);
-      }
-      pos += (uint32_t)__popcll(mk[u][j]);
-    }
+  for (int i = 0; i < 4 * V; ++i) {
+    const bool ok = valid[i / 4];
+    const bool in = ok && g[i] < (uint32_t)c.m;
+    c.bad |= ok && !in;
+    const bool h = in && g[i] < (uint32_t)c.t;
+    cold[i] = in && !h;
+    group_hot_or_sink(c, h, g[i], v[i], hot_sink);
+  }
+  cold_append(o, g, cold, [&](int i, int32_t idx) {
+    buffer_store_record((int32_t)g[i], seg.keys, idx, 0, 0, 0);
+    buffer_store_record(v[i], seg.vals, idx, 0, 0, 0);
+  });
 }
 
-__device__ __forceinline__ void group_split_one(GroupCtx &c, const PairSink &o, bool valid, int32_t g, int32_t v) {
-  const bool in = valid && (uint32_t)g < (uint32_t)c.m;
-  if (valid && !in) c.bad = true;
-  const bool h = in && g < c.t;
-  const bool cd = in && !h;
-  if (h) group_hot(c, g, v);
-  const uint64_t m = __ballot(cd);
-  if (m) {
-    const uint32_t base = wave_reserve(o.count, (uint32_t)__popcll(m));
-    if (cd) {
-      const uint32_t idx = base + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
-      if (idx < o.cap) {
-        o.keys[idx] = g;
-        o.vals[idx] = v;
-      }
-      lds_add_u32(&o.hist[(uint32_t)(g - c.t) >> o.wshift], 1u);
-    }
-  }
+__device__ __forceinline__ void group_split_one(GroupCtx &c, const ColdSink &o, const PairSeg &seg, uint32_t hot_sink,
+                                                bool valid, int32_t gi, int32_t v) {
+  const uint32_t g[1] = {(uint32_t)gi};
+  const bool in = valid && g[0] < (uint32_t)c.m;
+  c.bad |= valid && !in;
+  const bool h = in && g[0] < (uint32_t)c.t;
+  const bool cold[1] = {in && !h};
+  group_hot_or_sink(c, h, g[0], v, hot_sink);
+  cold_append(o, g, cold, [&](int, int32_t idx) {
+    buffer_store_record(gi, seg.keys, idx, 0, 0, 0);
+    buffer_store_record(v, seg.vals, idx, 0, 0, 0);
+  });
 }
 
 __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
@@ -308,19 +279,22 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
   c.acc_sum = acc_sum;
   c.acc_cnt = acc_cnt;
   c.bad = false;
-  group_range_init(c, smem, t);
-  uint32_t *lhist = c.hot_cnt + kCopySlots + t;
-  uint32_t *lcount = lhist + P;
-  for (int p = threadIdx.x; p < P; p += blockDim.x) lhist[p] = 0;
+  group_range_init(c, smem, t, kWave);
+  uint32_t *lhist = c.hot_cnt + kCopySlots + t + kWave;
+  uint32_t *lcount = lhist + P + kWave;
+  for (int p = threadIdx.x; p < P + kWave; p += blockDim.x) lhist[p] = 0;
   if (threadIdx.x == 0) *lcount = 0;
   __syncthreads();
-  PairSink o;
-  o.keys = seg_keys + (int64_t)blockIdx.x * seg_cap;
-  o.vals = seg_vals + (int64_t)blockIdx.x * seg_cap;
-  o.cap = seg_cap;
+  ColdSink o;
   o.count = lcount;
   o.hist = lhist;
+  o.t = (uint32_t)t;
   o.wshift = wshift;
+  o.sink = (uint32_t)P + lane_id();
+  PairSeg seg;
+  seg.keys = record_buffer(seg_keys + (int64_t)blockIdx.x * seg_cap, (uint32_t)seg_cap);
+  seg.vals = record_buffer(seg_vals + (int64_t)blockIdx.x * seg_cap, (uint32_t)seg_cap);
+  const uint32_t hot_sink = (uint32_t)(kCopySlots + t) + lane_id();
 
   // Workgroup b owns rows [b * per, (b + 1) * per) (in 4-row vectors when the
   // two columns are aligned together, else in single rows).
@@ -332,35 +306,50 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
       if (blockIdx.x == 0 && threadIdx.x < sp.head) i = threadIdx.x;
       if (blockIdx.x == gridDim.x - 1 && threadIdx.x >= 64 && threadIdx.x - 64 < n - sp.tail)
         i = sp.tail + threadIdx.x - 64;
-      group_split_one(c, o, i >= 0, i >= 0 ? keys[i] : 0, i >= 0 ? vals[i] : 0);
+      group_split_one(c, o, seg, hot_sink, i >= 0, i >= 0 ? keys[i] : 0, i >= 0 ? vals[i] : 0);
     }
     const int64_t per = (sp.nvec + gridDim.x - 1) / gridDim.x;
     const int64_t vb = (int64_t)blockIdx.x * per < sp.nvec ? (int64_t)blockIdx.x * per : sp.nvec;
     const int64_t ve = vb + per < sp.nvec ? vb + per : sp.nvec;
     const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
     const i32x4 *vv = reinterpret_cast<const i32x4 *>(vals + sp.head);
-    const int64_t tile_vecs = (int64_t)kGroupThreads * kGroupUnroll;
-    const bool all_valid[kGroupUnroll] = {true, true};
-    for (int64_t base = vb; base < ve; base += tile_vecs) {
-      i32x4 x[kGroupUnroll], y[kGroupUnroll];
-      if (base + tile_vecs <= ve) {
+    const int64_t tile_vecs = (int64_t)kGroupThreads * kSplitVecs;
+    const int64_t full_end = vb + ((ve - vb) / tile_vecs) * tile_vecs;
+    bool all_valid[kSplitVecs];
 #pragma unroll
-        for (int u = 0; u < kGroupUnroll; ++u) {
-          x[u] = load_stream4(vk + base + u * kGroupThreads + threadIdx.x);
-          y[u] = load_stream4(vv + base + u * kGroupThreads + threadIdx.x);
-        }
-        group_split_batch<kGroupUnroll, false>(c, o, x, y, all_valid);
-      } else {
-        bool valid[kGroupUnroll];
+    for (int u = 0; u < kSplitVecs; ++u) all_valid[u] = true;
+    auto load_tile = [&](i32x4(&x)[kSplitVecs], i32x4(&y)[kSplitVecs], int64_t base) {
 #pragma unroll
-        for (int u = 0; u < kGroupUnroll; ++u) {
-          const int64_t vi = base + u * kGroupThreads + threadIdx.x;
-          valid[u] = vi < ve;
-          x[u] = valid[u] ? load_stream4(vk + vi) : i32x4{0, 0, 0, 0};
-          y[u] = valid[u] ? load_stream4(vv + vi) : i32x4{0, 0, 0, 0};
-        }
-        group_split_batch<kGroupUnroll, true>(c, o, x, y, valid);
+      for (int u = 0; u < kSplitVecs; ++u) {
+        x[u] = load_stream4(vk + base + u * kGroupThreads + threadIdx.x);
+        y[u] = load_stream4(vv + base + u * kGroupThreads + threadIdx.x);
       }
+    };
+    i32x4 xa[kSplitVecs], ya[kSplitVecs], xb[kSplitVecs], yb[kSplitVecs];
+    int64_t base = vb;
+    if (base < full_end) load_tile(xa, ya, base);
+    while (base < full_end) {  // the next tile is loaded while the current one is processed
+      int64_t nxt = base + tile_vecs;
+      load_tile(xb, yb, nxt < full_end ? nxt : base);
+      group_split_batch<kSplitVecs>(c, o, seg, hot_sink, xa, ya, all_valid);
+      base = nxt;
+      if (base >= full_end) break;
+      nxt = base + tile_vecs;
+      load_tile(xa, ya, nxt < full_end ? nxt : base);
+      group_split_batch<kSplitVecs>(c, o, seg, hot_sink, xb, yb, all_valid);
+      base = nxt;
+    }
+    if (full_end < ve) {  // last partial tile
+      i32x4 x[kSplitVecs], y[kSplitVecs];
+      bool valid[kSplitVecs];
+#pragma unroll
+      for (int u = 0; u < kSplitVecs; ++u) {
+        const int64_t vi = full_end + u * kGroupThreads + threadIdx.x;
+        valid[u] = vi < ve;
+        x[u] = valid[u] ? load_stream4(vk + vi) : i32x4{0, 0, 0, 0};
+        y[u] = valid[u] ? load_stream4(vv + vi) : i32x4{0, 0, 0, 0};
+      }
+      group_split_batch<kSplitVecs>(c, o, seg, hot_sink, x, y, valid);
     }
   } else {
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
@@ -369,7 +358,8 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
     for (int64_t base = rb; base < re; base += blockDim.x) {
       const int64_t i = base + threadIdx.x;
       const bool valid = i < re;
-      group_split_one(c, o, valid, valid ? load_stream1(keys + i) : 0, valid ? load_stream1(vals + i) : 0);
+      group_split_one(c, o, seg, hot_sink, valid, valid ? load_stream1(keys + i) : 0,
+                      valid ? load_stream1(vals + i) : 0);
     }
   }
   if (c.bad) *flag = 1;
@@ -380,11 +370,16 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Partitioned form, pass 3: the (group, value) pairs of each unit are summed
-// in LDS bins of their slice (W groups); the bins are flushed into the shared
-// accumulators when the workgroup moves to another slice and at the end.
+// Partitioned form, pass 3: the slice-ordered pairs are cut evenly into one
+// contiguous range per workgroup; the workgroup sums the pairs of each slice
+// its range touches in LDS bins (W groups) and flushes the bins into the
+// shared accumulators before it moves to the next slice.
 // ---------------------------------------------------------------------------
-constexpr int kSliceUnroll = 8;
+constexpr int kSliceVecs = 4;
+
+struct PairVec {
+  i32x4 k, v;
+};
 
 __device__ __forceinline__ void slice_flush(uint64_t *bsum, uint32_t *bcnt, int32_t slen, int64_t sbase,
                                             uint64_t *acc_sum, uint64_t *acc_cnt) {
@@ -401,81 +396,62 @@ __device__ __forceinline__ void slice_flush(uint64_t *bsum, uint32_t *bcnt, int3
 
 __global__ __launch_bounds__(kGroupThreads) void group_slice_kernel(
     const int32_t *__restrict__ keys, const int32_t *__restrict__ vals, const uint32_t *__restrict__ slice_off,
-    const uint32_t *__restrict__ unit_start, int32_t P, int32_t m, int32_t t, int32_t wshift,
-    uint64_t *__restrict__ acc_sum, uint64_t *__restrict__ acc_cnt) {
+    int32_t P, int32_t m, int32_t t, int32_t wshift, uint64_t *__restrict__ acc_sum, uint64_t *__restrict__ acc_cnt) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int32_t W = 1 << wshift;
   uint64_t *bsum = reinterpret_cast<uint64_t *>(smem);
   uint32_t *bcnt = reinterpret_cast<uint32_t *>(bsum + W);
-  uint32_t *ustart = bcnt + W;
-  uint32_t *soff = ustart + (P + 1);
+  uint32_t *soff = bcnt + W;
   for (int i = threadIdx.x; i < W; i += blockDim.x) {
     bsum[i] = 0;
     bcnt[i] = 0;
   }
-  for (int p = threadIdx.x; p <= P; p += blockDim.x) {
-    ustart[p] = unit_start[p];
-    soff[p] = slice_off[p];
-  }
+  for (int p = threadIdx.x; p <= P; p += blockDim.x) soff[p] = slice_off[p];
   __syncthreads();
-  const uint32_t units = ustart[P];
-  const uint32_t u0 = (uint32_t)((uint64_t)units * blockIdx.x / gridDim.x);
-  const uint32_t u1 = (uint32_t)((uint64_t)units * (blockIdx.x + 1) / gridDim.x);
-  int32_t p = 0, cur = -1;
-  int64_t cur_base = 0;
-  int32_t cur_len = 0;
-  for (uint32_t u = u0; u < u1; ++u) {
-    while (p + 1 < P && ustart[p + 1] <= u) ++p;
-    if (p != cur) {
-      if (cur >= 0) {
-        __syncthreads();
-        slice_flush(bsum, bcnt, cur_len, cur_base, acc_sum, acc_cnt);
-      }
-      cur = p;
-      cur_base = (int64_t)t + ((int64_t)p << wshift);
-      cur_len = (int32_t)((int64_t)m - cur_base < W ? (int64_t)m - cur_base : W);
-      __syncthreads();
+  const uint32_t total = soff[P];
+  const uint32_t lo = (uint32_t)((uint64_t)total * blockIdx.x / gridDim.x);
+  const uint32_t hi = (uint32_t)((uint64_t)total * (blockIdx.x + 1) / gridDim.x);
+  int32_t p = 0;
+  {  // last slice that starts at or before lo
+    int32_t a = 0, b = P;
+    while (b - a > 1) {
+      const int32_t mid = (a + b) >> 1;
+      if (soff[mid] <= lo) a = mid;
+      else b = mid;
     }
-    const uint32_t lo = soff[p] + (u - ustart[p]) * kUnitItems;
-    const uint32_t hi = lo + kUnitItems < soff[p + 1] ? lo + kUnitItems : soff[p + 1];
-    const uint32_t smax = (uint32_t)cur_len - 1;
-    constexpr uint32_t kChunk = kSliceUnroll * kGroupThreads;
-    uint32_t i = lo + threadIdx.x;
-    const uint32_t full = lo + ((hi - lo) / kChunk) * kChunk;
-    int32_t g[kSliceUnroll], v[kSliceUnroll], gn[kSliceUnroll], vn[kSliceUnroll];
-    auto load = [&](int32_t(&gg)[kSliceUnroll], int32_t(&vv)[kSliceUnroll], uint32_t at) {
-#pragma unroll
-      for (int j = 0; j < kSliceUnroll; ++j) {
-        gg[j] = load_stream1(keys + at + j * kGroupThreads);
-        vv[j] = load_stream1(vals + at + j * kGroupThreads);
-      }
-    };
-    if (i < full) load(g, v, i);
-    for (; i < full; i += kChunk) {
-      load(gn, vn, i + kChunk < full ? i + kChunk : i);
-#pragma unroll
-      for (int j = 0; j < kSliceUnroll; ++j) {
-        uint32_t local = (uint32_t)(g[j] - (int32_t)cur_base);
-        local = local < smax ? local : smax;
-        lds_add_u64(&bsum[local], (uint64_t)(int64_t)v[j]);
-        lds_add_u32(&bcnt[local], 1u);
-      }
-#pragma unroll
-      for (int j = 0; j < kSliceUnroll; ++j) {
-        g[j] = gn[j];
-        v[j] = vn[j];
-      }
-    }
-    for (; i < hi; i += kGroupThreads) {
-      uint32_t local = (uint32_t)(load_stream1(keys + i) - (int32_t)cur_base);
-      local = local < smax ? local : smax;
-      lds_add_u64(&bsum[local], (uint64_t)(int64_t)load_stream1(vals + i));
-      lds_add_u32(&bcnt[local], 1u);
-    }
+    p = a;
   }
-  if (cur >= 0) {
+  const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys);
+  const i32x4 *vv = reinterpret_cast<const i32x4 *>(vals);
+  for (uint32_t at = lo; at < hi; ++p) {
+    const uint32_t end = soff[p + 1] < hi ? soff[p + 1] : hi;
+    if (end <= at) continue;
+    const int64_t sbase = (int64_t)t + ((int64_t)p << wshift);
+    const int32_t slen = (int32_t)((int64_t)m - sbase < W ? (int64_t)m - sbase : W);
+    const uint32_t smax = (uint32_t)slen - 1;
+    auto add = [&](int32_t g, int32_t v) {
+      uint32_t local = (uint32_t)(g - (int32_t)sbase);
+      local = local < smax ? local : smax;
+      lds_add_u64(&bsum[local], (uint64_t)(int64_t)v);
+      lds_add_u32(&bcnt[local], 1u);
+    };
+    walk_items<kSliceVecs, kGroupThreads, PairVec>(
+        at, end, [&](uint32_t i) { add(keys[i], vals[i]); },
+        [&](uint32_t vi) { return PairVec{load_stream4(vk + vi), load_stream4(vv + vi)}; },
+        [&](const PairVec(&x)[kSliceVecs], const bool(&valid)[kSliceVecs]) {
+#pragma unroll
+          for (int u = 0; u < kSliceVecs; ++u) {
+            if (!valid[u]) continue;
+            add(x[u].k.x, x[u].v.x);
+            add(x[u].k.y, x[u].v.y);
+            add(x[u].k.z, x[u].v.z);
+            add(x[u].k.w, x[u].v.w);
+          }
+        });
     __syncthreads();
-    slice_flush(bsum, bcnt, cur_len, cur_base, acc_sum, acc_cnt);
+    slice_flush(bsum, bcnt, slen, sbase, acc_sum, acc_cnt);
+    __syncthreads();
+    at = end;
   }
 }
 
@@ -514,7 +490,8 @@ size_t group_lds_bytes(int32_t hot_groups) {
 }
 
 int32_t group_max_hot_groups(const DeviceInfo &dev) {
-  const size_t fixed = group_lds_bytes(0) + (size_t)(kMaxSlices + 4) * 4;  // + slice histogram of pass 1
+  // + sink slots and slice histogram of pass 1
+  const size_t fixed = group_lds_bytes(0) + (size_t)kWave * 12 + (size_t)(kMaxSlices + kWave + 4) * 4;
   if (dev.lds_per_block <= fixed) return 0;
   return (int32_t)((dev.lds_per_block - fixed) / 12);
 }
@@ -615,8 +592,8 @@ hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact
       tab.slice_off = (uint32_t *)ws;
       ws += r((size_t)(pl.slices + 1) * 4);
       tab.unit_start = (uint32_t *)ws;
-      const size_t lds1 = group_lds_bytes(t) + (size_t)(pl.slices + 4) * 4;
-      const size_t lds3 = ((size_t)12 << pl.wshift) + (size_t)2 * (pl.slices + 1) * 4;
+      const size_t lds1 = group_lds_bytes(t) + (size_t)kWave * 12 + (size_t)(pl.slices + kWave + 4) * 4;
+      const size_t lds3 = ((size_t)12 << pl.wshift) + (size_t)(pl.slices + 1) * 4;
       allow_lds(group_split_kernel, lds1);
       allow_lds(group_slice_kernel, lds3);
       for (int64_t off = 0; off < n_fact; off += pl.round) {
@@ -638,7 +615,7 @@ hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact
         if (e != hipSuccess) return e;
         st = stage_begin("group_slice", s);
         hipLaunchKernelGGL(group_slice_kernel, dim3(pl.blocks), dim3(kGroupThreads), lds3, s, items_k, items_v,
-                           tab.slice_off, tab.unit_start, pl.slices, n_groups, t, pl.wshift, acc_sum, acc_cnt);
+                           tab.slice_off, pl.slices, n_groups, t, pl.wshift, acc_sum, acc_cnt);
         e = hipGetLastError();
         stage_end(st, s);
         if (e != hipSuccess) return e;

@@ -94,6 +94,22 @@ __device__ __forceinline__ void join_slow(JoinCtx<GROUPS> &c, uint32_t uk) {
   }
 }
 
+// The rare slow path of a batch: one loop over its slots instead of a copy
+// of join_slow per slot, so the common path stays small.
+template <int GROUPS, int N>
+__device__ __forceinline__ void join_slow_batch(JoinCtx<GROUPS> &c, const uint32_t (&w)[N], const uint32_t (&k)[N]) {
+#pragma unroll 1
+  for (int s = 0; s < N; ++s) {
+    uint32_t ws = w[0], ks = k[0];
+#pragma unroll
+    for (int q = 1; q < N; ++q) {
+      ws = s == q ? w[q] : ws;
+      ks = s == q ? k[q] : ks;
+    }
+    if (!ws) join_slow(c, ks);
+  }
+}
+
 // Workgroup reduction of the accumulators, then one global atomic per group.
 template <int GROUPS>
 __device__ __forceinline__ void join_flush(JoinCtx<GROUPS> &c, int32_t *flag) {
@@ -173,32 +189,21 @@ __device__ __forceinline__ uint32_t fetch_hot_or_global(const HotCtx &h, uint32_
 // ---------------------------------------------------------------------------
 template <int GROUPS, int V>
 __device__ __forceinline__ void join_batch(JoinCtx<GROUPS> &c, const HotCtx &h, const i32x4 (&x)[V]) {
-  uint32_t w[V][4];
+  uint32_t k[4 * V], w[4 * V];
 #pragma unroll
   for (int u = 0; u < V; ++u) {
-    w[u][0] = fetch_hot_or_global(h, (uint32_t)x[u].x);
-    w[u][1] = fetch_hot_or_global(h, (uint32_t)x[u].y);
-    w[u][2] = fetch_hot_or_global(h, (uint32_t)x[u].z);
-    w[u][3] = fetch_hot_or_global(h, (uint32_t)x[u].w);
+    k[4 * u] = (uint32_t)x[u].x, k[4 * u + 1] = (uint32_t)x[u].y;
+    k[4 * u + 2] = (uint32_t)x[u].z, k[4 * u + 3] = (uint32_t)x[u].w;
   }
+#pragma unroll
+  for (int i = 0; i < 4 * V; ++i) w[i] = fetch_hot_or_global(h, k[i]);
   uint32_t all = kValid;
 #pragma unroll
-  for (int u = 0; u < V; ++u) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      all &= w[u][j];
-      join_add(c, w[u][j]);
-    }
+  for (int i = 0; i < 4 * V; ++i) {
+    all &= w[i];
+    join_add(c, w[i]);
   }
-  if (__builtin_expect(!(all & kValid), 0)) {  // an escape or out-of-range key in this batch
-#pragma unroll
-    for (int u = 0; u < V; ++u) {
-      if (!w[u][0]) join_slow(c, (uint32_t)x[u].x);
-      if (!w[u][1]) join_slow(c, (uint32_t)x[u].y);
-      if (!w[u][2]) join_slow(c, (uint32_t)x[u].z);
-      if (!w[u][3]) join_slow(c, (uint32_t)x[u].w);
-    }
-  }
+  if (__builtin_expect(!(all & kValid), 0)) join_slow_batch(c, w, k);  // an escape or out-of-range key
 }
 
 template <int GROUPS>
@@ -273,107 +278,47 @@ __global__ __launch_bounds__(kJoinThreads) void join_kernel(const int32_t *__res
 // owns a contiguous range of the column, so its segment needs no more slots
 // than the rows it reads.
 // ---------------------------------------------------------------------------
-struct ColdSink {
-  int32_t *seg;         // this workgroup's segment
-  int64_t seg_cap;
-  uint32_t *count;      // LDS: items written so far
-  uint32_t *hist;       // LDS [P]
-  uint32_t t;
-  int32_t wshift;
-};
-
-__device__ __forceinline__ uint32_t wave_reserve(uint32_t *count, uint32_t n) {
-  // One LDS atomic per wave: the first active lane reserves n slots.
-  uint32_t base = 0;
-  const uint64_t act = __ballot(1);
-  const int leader = __ffsll((unsigned long long)act) - 1;
-  if (lane_id() == leader) base = atomicAdd(count, n);
-  return __shfl(base, leader, kWave);
-}
-
 template <int GROUPS, int V, bool GUARD>
-__device__ __forceinline__ void join_split_batch(JoinCtx<GROUPS> &c, const ColdSink &o, const uint32_t *hot,
-                                                 uint32_t tclamp, const i32x4 (&x)[V], const bool (&valid)[V]) {
-  uint32_t w[V][4], kk[V][4];
-  bool cold[V][4];
+__device__ __forceinline__ void join_split_batch(JoinCtx<GROUPS> &c, const ColdSink &o, rsrc_t seg,
+                                                 const uint32_t *hot, uint32_t tclamp, const i32x4 (&x)[V],
+                                                 const bool (&valid)[V]) {
+  uint32_t k[4 * V], w[4 * V];
+  bool cold[4 * V];
 #pragma unroll
   for (int u = 0; u < V; ++u) {
-    kk[u][0] = (uint32_t)x[u].x, kk[u][1] = (uint32_t)x[u].y, kk[u][2] = (uint32_t)x[u].z, kk[u][3] = (uint32_t)x[u].w;
+    k[4 * u] = (uint32_t)x[u].x, k[4 * u + 1] = (uint32_t)x[u].y;
+    k[4 * u + 2] = (uint32_t)x[u].z, k[4 * u + 3] = (uint32_t)x[u].w;
   }
 #pragma unroll
-  for (int u = 0; u < V; ++u) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t k = kk[u][j];
-      const bool ok = !GUARD || valid[u];
-      const bool h = ok && k < o.t;
-      cold[u][j] = ok && !h && k < c.n_rows;
-      if (ok && k >= c.n_rows) c.bad = true;
-      const uint32_t wl = hot[k < tclamp ? k : tclamp];
-      w[u][j] = h ? wl : kValid;
-    }
+  for (int i = 0; i < 4 * V; ++i) {
+    const bool ok = !GUARD || valid[i / 4];
+    const bool h = ok && k[i] < o.t;
+    cold[i] = ok && !h && k[i] < c.n_rows;
+    c.bad |= ok && k[i] >= c.n_rows;
+    const uint32_t wl = hot[k[i] < tclamp ? k[i] : tclamp];
+    w[i] = h ? wl : kValid;
   }
   uint32_t all = kValid;
 #pragma unroll
-  for (int u = 0; u < V; ++u) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      all &= w[u][j];
-      join_add(c, w[u][j]);
-    }
+  for (int i = 0; i < 4 * V; ++i) {
+    all &= w[i];
+    join_add(c, w[i]);
   }
-  if (__builtin_expect(!(all & kValid), 0)) {  // a hot row whose price needs the slow path
-#pragma unroll
-    for (int u = 0; u < V; ++u)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (!w[u][j]) join_slow(c, kk[u][j]);
-  }
-  // Compact the cold keys: slot order within the wave, one reservation per wave.
-  uint64_t m[V][4];
-  uint32_t total = 0;
-#pragma unroll
-  for (int u = 0; u < V; ++u)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      m[u][j] = __ballot(cold[u][j]);
-      total += (uint32_t)__popcll(m[u][j]);
-    }
-  if (total == 0) return;
-  uint32_t pos = wave_reserve(o.count, total);
-  const uint64_t lt = (1ull << lane_id()) - 1ull;
-#pragma unroll
-  for (int u = 0; u < V; ++u)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (cold[u][j]) {
-        const uint32_t idx = pos + (uint32_t)__popcll(m[u][j] & lt);
-        const uint32_t k = kk[u][j];
-        if (idx < o.seg_cap) o.seg[idx] = (int32_t)k;
-        lds_add_u32(&o.hist[(k - o.t) >> o.wshift], 1u);
-      }
-      pos += (uint32_t)__popcll(m[u][j]);
-    }
+  if (__builtin_expect(!(all & kValid), 0)) join_slow_batch(c, w, k);  // a hot row whose price escapes
+  cold_append(o, k, cold, [&](int i, int32_t idx) { buffer_store_record((int32_t)k[i], seg, idx, 0, 0, 0); });
 }
 
 template <int GROUPS>
-__device__ __forceinline__ void join_split_one(JoinCtx<GROUPS> &c, const ColdSink &o, const uint32_t *hot,
-                                               uint32_t tclamp, bool valid, uint32_t k) {
+__device__ __forceinline__ void join_split_one(JoinCtx<GROUPS> &c, const ColdSink &o, rsrc_t seg,
+                                               const uint32_t *hot, uint32_t tclamp, bool valid, uint32_t k) {
   const bool h = valid && k < o.t;
-  const bool cd = valid && !h && k < c.n_rows;
-  if (valid && k >= c.n_rows) c.bad = true;
   const uint32_t w = h ? hot[k < tclamp ? k : tclamp] : kValid;
+  c.bad |= valid && k >= c.n_rows;
   join_add(c, w);
   if (!w) join_slow(c, k);
-  const uint64_t m = __ballot(cd);
-  if (m) {
-    const uint32_t base = wave_reserve(o.count, (uint32_t)__popcll(m));
-    if (cd) {
-      const uint32_t idx = base + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
-      if (idx < o.seg_cap) o.seg[idx] = (int32_t)k;
-      lds_add_u32(&o.hist[(k - o.t) >> o.wshift], 1u);
-    }
-  }
+  const uint32_t kk[1] = {k};
+  const bool cd[1] = {valid && !h && k < c.n_rows};
+  cold_append(o, kk, cd, [&](int, int32_t idx) { buffer_store_record((int32_t)k, seg, idx, 0, 0, 0); });
 }
 
 template <int GROUPS>
@@ -389,20 +334,20 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
   uint32_t *hot = reinterpret_cast<uint32_t *>(smem + kBinBytes);
   const int32_t hot_words = (t_lds + 4) & ~3;  // at least one word, 16-byte multiple
   uint32_t *lhist = hot + hot_words;
-  uint32_t *lcount = lhist + P;
+  uint32_t *lcount = lhist + P + kWave;
   stage_words(hot, words, 0, t_lds);
   if (t_lds == 0 && threadIdx.x == 0) hot[0] = 0;
-  for (int p = threadIdx.x; p < P; p += blockDim.x) lhist[p] = 0;
+  for (int p = threadIdx.x; p < P + kWave; p += blockDim.x) lhist[p] = 0;
   if (threadIdx.x == 0) *lcount = 0;
   __syncthreads();
 
+  const rsrc_t seg = record_buffer(cold_seg + (int64_t)blockIdx.x * seg_cap, (uint32_t)seg_cap);
   ColdSink o;
-  o.seg = cold_seg + (int64_t)blockIdx.x * seg_cap;
-  o.seg_cap = seg_cap;
   o.count = lcount;
   o.hist = lhist;
   o.t = (uint32_t)t_lds;
   o.wshift = wshift;
+  o.sink = (uint32_t)P + lane_id();
   const uint32_t tclamp = t_lds > 0 ? (uint32_t)t_lds - 1 : 0u;
 
   // Contiguous range of key vectors per workgroup; block 0 takes the scalar
@@ -416,7 +361,7 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
     if (blockIdx.x == 0 && threadIdx.x < sp.head) i = threadIdx.x;
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x >= 64 && threadIdx.x - 64 < n - sp.tail)
       i = sp.tail + threadIdx.x - 64;
-    join_split_one(c, o, hot, tclamp, i >= 0, i >= 0 ? (uint32_t)keys[i] : 0u);
+    join_split_one(c, o, seg, hot, tclamp, i >= 0, i >= 0 ? (uint32_t)keys[i] : 0u);
   }
 
   const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
@@ -434,12 +379,12 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
   while (base < full_end) {
     int64_t nxt = base + tile_vecs;
     load_tile(xb, nxt < full_end ? nxt : base);
-    join_split_batch<GROUPS, kJoinVecs, false>(c, o, hot, tclamp, xa, all_valid);
+    join_split_batch<GROUPS, kJoinVecs, false>(c, o, seg, hot, tclamp, xa, all_valid);
     base = nxt;
     if (base >= full_end) break;
     nxt = base + tile_vecs;
     load_tile(xa, nxt < full_end ? nxt : base);
-    join_split_batch<GROUPS, kJoinVecs, false>(c, o, hot, tclamp, xb, all_valid);
+    join_split_batch<GROUPS, kJoinVecs, false>(c, o, seg, hot, tclamp, xb, all_valid);
     base = nxt;
   }
   if (full_end < ve) {  // last partial tile
@@ -451,7 +396,7 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
       valid[u] = vi < ve;
       x[u] = valid[u] ? load_stream4(vk + vi) : i32x4{0, 0, 0, 0};
     }
-    join_split_batch<GROUPS, kJoinVecs, true>(c, o, hot, tclamp, x, valid);
+    join_split_batch<GROUPS, kJoinVecs, true>(c, o, seg, hot, tclamp, x, valid);
   }
   __syncthreads();
   if (threadIdx.x == 0) seg_count[blockIdx.x] = *lcount < seg_cap ? *lcount : (uint32_t)seg_cap;
@@ -460,104 +405,114 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Partitioned form, pass 3: units of slice-ordered cold keys.  Workgroup b
-// takes a contiguous range of units, so consecutive units usually share a
-// slice and the slice is copied into LDS once.  Slices with few keys are
-// gathered from global memory instead.
+// Partitioned form, pass 3: the slice-ordered cold keys are cut evenly into
+// one contiguous range per workgroup; the workgroup walks the slices its range
+// touches, copies each into LDS when its share of the slice is large enough
+// to pay for the copy, and gathers the words from global memory otherwise.
 // ---------------------------------------------------------------------------
-constexpr int kSliceUnroll = 16;
+constexpr int kSliceVecs = 4;  // 16-byte key vectors per lane per batch
 
-// One unit of slice-ordered cold keys: DENSE reads the LDS copy of the slice,
-// otherwise the words are gathered from global memory.
 template <int GROUPS, bool DENSE>
-__device__ __forceinline__ void join_unit(JoinCtx<GROUPS> &c, const int32_t *__restrict__ items, uint32_t lo,
-                                          uint32_t hi, const uint32_t *slice, int32_t sbase, uint32_t smax,
-                                          rsrc_t wr) {
-  auto lookup = [&](int32_t k) -> uint32_t {
+struct SliceLookup {
+  const uint32_t *slice;  // LDS copy of rows [sbase, sbase + smax]
+  int32_t sbase;
+  uint32_t smax;
+  rsrc_t words;
+  __device__ __forceinline__ uint32_t operator()(uint32_t k) const {
     if (DENSE) {
-      const uint32_t local = (uint32_t)(k - sbase);
+      const uint32_t local = k - (uint32_t)sbase;
       return slice[local < smax ? local : smax];
     }
-    return buffer_load_record(wr, k, 0, 0, 0);
-  };
-  // Chunks of kSliceUnroll keys per lane; the next chunk is loaded while the
-  // current one is looked up.
-  constexpr uint32_t kChunk = kSliceUnroll * kJoinThreads;
-  uint32_t i = lo + threadIdx.x;
-  const uint32_t full = lo + ((hi - lo) / kChunk) * kChunk;
-  int32_t k[kSliceUnroll], kn[kSliceUnroll];
-  auto load = [&](int32_t(&kk)[kSliceUnroll], uint32_t at) {
-#pragma unroll
-    for (int j = 0; j < kSliceUnroll; ++j) kk[j] = load_stream1(items + at + j * kJoinThreads);
-  };
-  if (i < full) load(k, i);
-  for (; i < full; i += kChunk) {
-    load(kn, i + kChunk < full ? i + kChunk : i);
-    uint32_t w[kSliceUnroll];
-#pragma unroll
-    for (int j = 0; j < kSliceUnroll; ++j) w[j] = lookup(k[j]);
-    uint32_t all = kValid;
-#pragma unroll
-    for (int j = 0; j < kSliceUnroll; ++j) {
-      all &= w[j];
-      join_add(c, w[j]);
-    }
-    if (__builtin_expect(!(all & kValid), 0)) {
-#pragma unroll
-      for (int j = 0; j < kSliceUnroll; ++j)
-        if (!w[j]) join_slow(c, (uint32_t)k[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < kSliceUnroll; ++j) k[j] = kn[j];
+    return buffer_load_record(words, (int32_t)k, 0, 0, 0);
   }
-  for (; i < hi; i += kJoinThreads) {
-    const int32_t k = load_stream1(items + i);
-    const uint32_t w = lookup(k);
-    join_add(c, w);
-    if (!w) join_slow(c, (uint32_t)k);
+};
+
+template <int GROUPS, int V, class L>
+__device__ __forceinline__ void join_slice_batch(JoinCtx<GROUPS> &c, const L &look, const i32x4 (&x)[V],
+                                                 const bool (&valid)[V]) {
+  uint32_t k[4 * V], w[4 * V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    k[4 * u] = (uint32_t)x[u].x, k[4 * u + 1] = (uint32_t)x[u].y;
+    k[4 * u + 2] = (uint32_t)x[u].z, k[4 * u + 3] = (uint32_t)x[u].w;
   }
+#pragma unroll
+  for (int i = 0; i < 4 * V; ++i) {
+    w[i] = valid[i / 4] ? look(k[i]) : kValid;
+  }
+  uint32_t all = kValid;
+#pragma unroll
+  for (int i = 0; i < 4 * V; ++i) {
+    all &= w[i];
+    join_add(c, w[i]);
+  }
+  if (__builtin_expect(!(all & kValid), 0)) join_slow_batch(c, w, k);
+}
+
+template <int GROUPS, class L>
+__device__ __forceinline__ void join_slice_range(JoinCtx<GROUPS> &c, const L &look, const int32_t *__restrict__ items,
+                                                 uint32_t lo, uint32_t hi) {
+  const i32x4 *vk = reinterpret_cast<const i32x4 *>(items);
+  walk_items<kSliceVecs, kJoinThreads, i32x4>(
+      lo, hi,
+      [&](uint32_t i) {
+        const uint32_t k = (uint32_t)items[i];
+        const uint32_t w = look(k);
+        join_add(c, w);
+        if (!w) join_slow(c, k);
+      },
+      [&](uint32_t vi) { return load_stream4(vk + vi); },
+      [&](const i32x4(&x)[kSliceVecs], const bool(&valid)[kSliceVecs]) {
+        join_slice_batch<GROUPS, kSliceVecs>(c, look, x, valid);
+      });
 }
 
 template <int GROUPS>
 __global__ __launch_bounds__(kJoinThreads) void join_slice_kernel(
-    const int32_t *__restrict__ items, const uint32_t *__restrict__ slice_off, const uint32_t *__restrict__ unit_start,
-    int32_t P, const uint32_t *__restrict__ words, int32_t n_rows, int32_t t, int32_t wshift,
-    const int32_t *__restrict__ price, const int8_t *__restrict__ cat, int32_t cat_lt, int64_t *__restrict__ out_sum,
-    int64_t *__restrict__ out_cnt, int32_t *flag) {
+    const int32_t *__restrict__ items, const uint32_t *__restrict__ slice_off, int32_t P,
+    const uint32_t *__restrict__ words, int32_t n_rows, int32_t t, int32_t wshift, const int32_t *__restrict__ price,
+    const int8_t *__restrict__ cat, int32_t cat_lt, int64_t *__restrict__ out_sum, int64_t *__restrict__ out_cnt,
+    int32_t *flag) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int kBinBytes = GROUPS == 16 ? kJoinBins * kWave * 8 : 0;
   JoinCtx<GROUPS> c;
   join_init(c, smem, price, cat, cat_lt, n_rows, out_sum, out_cnt);
   const int32_t W = 1 << wshift;
   uint32_t *slice = reinterpret_cast<uint32_t *>(smem + kBinBytes);
-  uint32_t *ustart = slice + W;
-  uint32_t *soff = ustart + (P + 1);
-  for (int p = threadIdx.x; p <= P; p += blockDim.x) {
-    ustart[p] = unit_start[p];
-    soff[p] = slice_off[p];
-  }
+  uint32_t *soff = slice + W;
+  for (int p = threadIdx.x; p <= P; p += blockDim.x) soff[p] = slice_off[p];
   __syncthreads();
   const rsrc_t wr = record_buffer(words, (uint32_t)n_rows);
-  const uint32_t units = ustart[P];
-  const uint32_t u0 = (uint32_t)((uint64_t)units * blockIdx.x / gridDim.x);
-  const uint32_t u1 = (uint32_t)((uint64_t)units * (blockIdx.x + 1) / gridDim.x);
+  const uint32_t total = soff[P];
+  const uint32_t lo = (uint32_t)((uint64_t)total * blockIdx.x / gridDim.x);
+  const uint32_t hi = (uint32_t)((uint64_t)total * (blockIdx.x + 1) / gridDim.x);
+  // first slice that ends after lo
   int32_t p = 0;
-  int32_t loaded = -1;
-  for (uint32_t u = u0; u < u1; ++u) {
-    while (p + 1 < P && ustart[p + 1] <= u) ++p;
-    const uint32_t lo = soff[p] + (u - ustart[p]) * kUnitItems;
-    const uint32_t hi = lo + kUnitItems < soff[p + 1] ? lo + kUnitItems : soff[p + 1];
+  {
+    int32_t a = 0, b = P;  // soff[a] <= lo < soff[b] for non-empty ranges
+    while (b - a > 1) {
+      const int32_t m = (a + b) >> 1;
+      if (soff[m] <= lo) a = m;
+      else b = m;
+    }
+    p = a;
+  }
+  for (uint32_t at = lo; at < hi; ++p) {
+    const uint32_t end = soff[p + 1] < hi ? soff[p + 1] : hi;
+    if (end <= at) continue;
     const int64_t sbase = (int64_t)t + ((int64_t)p << wshift);
     const int32_t slen = (int32_t)((int64_t)n_rows - sbase < W ? (int64_t)n_rows - sbase : W);
-    const bool dense = (soff[p + 1] - soff[p]) >= (uint32_t)(W >> 3);
-    if (dense && loaded != p) {
+    if (end - at >= (uint32_t)(W >> 3)) {  // enough keys to pay for copying the slice
       __syncthreads();
       stage_words(slice, words, sbase, slen);
       __syncthreads();
-      loaded = p;
+      const SliceLookup<GROUPS, true> look{slice, (int32_t)sbase, (uint32_t)slen - 1, wr};
+      join_slice_range(c, look, items, at, end);
+    } else {
+      const SliceLookup<GROUPS, false> look{slice, (int32_t)sbase, (uint32_t)slen - 1, wr};
+      join_slice_range(c, look, items, at, end);
     }
-    if (dense) join_unit<GROUPS, true>(c, items, lo, hi, slice, (int32_t)sbase, (uint32_t)slen - 1, wr);
-    else join_unit<GROUPS, false>(c, items, lo, hi, slice, (int32_t)sbase, (uint32_t)slen - 1, wr);
+    at = end;
   }
   join_flush(c, flag);
 }
@@ -587,14 +542,15 @@ size_t join_lds_bytes(int groups, int32_t hot_rows) {
 
 int32_t join_max_hot_rows(int groups, const DeviceInfo &dev) {
   // bins + static reduction scratch + slice histogram of the partitioned form
-  const size_t fixed = join_lds_bytes(groups, 0) - 16 + 256 + (size_t)(kMaxSlices + 4) * 4;
+  const size_t fixed = join_lds_bytes(groups, 0) - 16 + 256 + (size_t)(kMaxSlices + kWave + 4) * 4;
   if (dev.lds_per_block <= fixed) return 0;
   return (int32_t)(((dev.lds_per_block - fixed) / 4) & ~(size_t)3) - 4;
 }
 
 JoinPlan join_plan(int64_t n_fact, int32_t n_rows, int32_t t, int groups, const DeviceInfo &dev) {
   JoinPlan pl;
-  pl.blocks = dev.cu_count > 0 ? dev.cu_count : 256;
+  // at least 16 workgroups, so that no accumulator bin sees 2^19 rows of a round
+  pl.blocks = dev.cu_count > 16 ? dev.cu_count : 16;
   pl.wshift = kJoinSliceShift;
   const int64_t cold_rows = (int64_t)n_rows - t;
   pl.slices = cold_rows > 0 ? (int32_t)((cold_rows + (1 << pl.wshift) - 1) >> pl.wshift) : 0;
@@ -679,9 +635,9 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
   ws += r((size_t)(pl.slices + 1) * 4);
   tab.unit_start = (uint32_t *)ws;
 
-  const size_t lds1 = join_lds_bytes(groups, t) + (size_t)(pl.slices + 4) * 4;
+  const size_t lds1 = join_lds_bytes(groups, t) + (size_t)(pl.slices + kWave + 4) * 4;
   const size_t lds3 = (groups == 16 ? (size_t)kJoinBins * kWave * 8 : 0) + ((size_t)4 << pl.wshift) +
-                      (size_t)2 * (pl.slices + 1) * 4;
+                      (size_t)(pl.slices + 1) * 4;
   if (groups == 16) {
     allow_lds(join_split_kernel<16>, lds1);
     allow_lds(join_slice_kernel<16>, lds3);
@@ -714,11 +670,11 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
     st = stage_begin("join_slice", s);
     if (groups == 16)
       hipLaunchKernelGGL(join_slice_kernel<16>, dim3(pl.blocks), dim3(kJoinThreads), lds3, s, items, tab.slice_off,
-                         tab.unit_start, pl.slices, words, n_rows, t, pl.wshift, price, cat, cat_lt, out_sum, out_cnt,
+                         pl.slices, words, n_rows, t, pl.wshift, price, cat, cat_lt, out_sum, out_cnt,
                          flag);
     else
       hipLaunchKernelGGL(join_slice_kernel<1>, dim3(pl.blocks), dim3(kJoinThreads), lds3, s, items, tab.slice_off,
-                         tab.unit_start, pl.slices, words, n_rows, t, pl.wshift, price, cat, cat_lt, out_sum, out_cnt,
+                         pl.slices, words, n_rows, t, pl.wshift, price, cat, cat_lt, out_sum, out_cnt,
                          flag);
     e = hipGetLastError();
     stage_end(st, s);

@@ -44,6 +44,11 @@ typedef int32_t rsrc_t __attribute__((ext_vector_type(4)));
 __device__ uint32_t buffer_load_record(rsrc_t rsrc, int32_t vindex, int32_t voffset, int32_t soffset,
                                        int32_t aux) __asm("llvm.amdgcn.struct.buffer.load.i32");
 
+// Structured buffer store of one 4-byte record; an index at or beyond the
+// record count is dropped by the same range check.
+__device__ void buffer_store_record(int32_t vdata, rsrc_t rsrc, int32_t vindex, int32_t voffset, int32_t soffset,
+                                    int32_t aux) __asm("llvm.amdgcn.struct.buffer.store.i32");
+
 __device__ __forceinline__ rsrc_t record_buffer(const void *base, uint32_t num_records) {
   const uint64_t a = (uint64_t)(uintptr_t)base;
   rsrc_t r;
@@ -74,5 +79,118 @@ struct SliceTables {       // in global memory (workspace)
   uint32_t *slice_off;     // [P + 1]: first item of slice p in slice order
   uint32_t *unit_start;    // [P + 1]: first unit of slice p
 };
+
+
+// ---------------------------------------------------------------------------
+// Cold-item compaction of pass 1.  Keys of the slots with cold[i] are
+// appended to the workgroup's segment in slot order within the wave (one LDS
+// reservation per 8 slots) and counted in their slice; the other lanes store
+// out of range (dropped) and count into a sink word of their own, so the code
+// has no per-slot branches.
+// ---------------------------------------------------------------------------
+struct ColdSink {
+  uint32_t *count;  // LDS: items written so far
+  uint32_t *hist;   // LDS [P + 64]: slice counts, then one sink word per lane
+  uint32_t t;
+  int32_t wshift;
+  uint32_t sink;    // P + lane
+};
+
+// Number of lanes below this one in mask m.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// One LDS atomic per wave: the first active lane reserves n slots and the
+// base is read back from that lane.
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t *count, uint32_t n) {
+  const uint64_t act = __ballot(1);
+  uint32_t base = 0;
+  if (lane_id() == (uint32_t)(__ffsll((unsigned long long)act) - 1)) base = atomicAdd(count, n);
+  return __builtin_amdgcn_readfirstlane(base);
+}
+
+// store(i, idx) writes slot i at segment index idx (idx = -1: out of range).
+template <int N, class Store>
+__device__ __forceinline__ void cold_append(const ColdSink &o, const uint32_t (&k)[N], const bool (&cold)[N],
+                                            Store store) {
+  constexpr int kPart = N < 8 ? N : 8;  // ballots live at once
+#pragma unroll
+  for (int p0 = 0; p0 < N; p0 += kPart) {
+    uint64_t m[kPart];
+    uint32_t total = 0;
+#pragma unroll
+    for (int i = 0; i < kPart; ++i) {
+      m[i] = __ballot(cold[p0 + i]);
+      total += (uint32_t)__popcll(m[i]);
+    }
+    if (total == 0) continue;
+    uint32_t pos = wave_reserve(o.count, total);
+#pragma unroll
+    for (int i = 0; i < kPart; ++i) {
+      const bool cd = cold[p0 + i];
+      store(p0 + i, cd ? (int32_t)(pos + lanes_below(m[i])) : -1);
+      lds_add_u32(&o.hist[cd ? (k[p0 + i] - o.t) >> o.wshift : o.sink], 1u);
+      pos += (uint32_t)__popcll(m[i]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Items [lo, hi) of 4-byte item arrays (16-byte aligned at item 0) visited by
+// a workgroup of THREADS threads: the at most 3 items before the first 16-byte
+// boundary (threads 0-2) and after the last one (threads 64-66) one at a time,
+// the rest in batches of V 16-byte vectors per thread, the next batch loaded
+// while the current one is processed, then one guarded partial batch.
+//   one(i)                       item i
+//   load(vi) -> T                vector vi (items 4 vi .. 4 vi + 3)
+//   batch(const T (&)[V], const bool (&valid)[V])
+// ---------------------------------------------------------------------------
+template <int V, int THREADS, class T, class One, class Load, class Batch>
+__device__ __forceinline__ void walk_items(uint32_t lo, uint32_t hi, One one, Load load, Batch batch) {
+  const uint32_t al = (lo + 3) & ~3u;
+  if (al >= hi) {
+    if (threadIdx.x < hi - lo) one(lo + threadIdx.x);
+    return;
+  }
+  if (threadIdx.x < al - lo) one(lo + threadIdx.x);
+  const uint32_t vb = al >> 2, ve = hi >> 2;
+  if (threadIdx.x >= kWave && threadIdx.x - kWave < hi - 4 * ve) one(4 * ve + threadIdx.x - kWave);
+
+  constexpr uint32_t kBatch = (uint32_t)V * THREADS;
+  const uint32_t full = vb + ((ve - vb) / kBatch) * kBatch;
+  bool all_valid[V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) all_valid[u] = true;
+  auto fill = [&](T(&x)[V], uint32_t at) {
+#pragma unroll
+    for (int u = 0; u < V; ++u) x[u] = load(at + u * THREADS + threadIdx.x);
+  };
+  T xa[V], xb[V];
+  uint32_t at = vb;
+  if (at < full) fill(xa, at);
+  while (at < full) {
+    uint32_t nxt = at + kBatch;
+    fill(xb, nxt < full ? nxt : at);  // unconditional: the last one re-reads the current batch
+    batch(xa, all_valid);
+    at = nxt;
+    if (at >= full) break;
+    nxt = at + kBatch;
+    fill(xa, nxt < full ? nxt : at);
+    batch(xb, all_valid);
+    at = nxt;
+  }
+  if (full < ve) {
+    T x[V];
+    bool valid[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const uint32_t vi = full + u * THREADS + threadIdx.x;
+      valid[u] = vi < ve;
+      x[u] = load(valid[u] ? vi : vb);
+    }
+    batch(x, valid);
+  }
+}
 
 }  // namespace skew
