@@ -370,15 +370,18 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Partitioned form, pass 3: the slice-ordered pairs are cut evenly into one
-// contiguous range per workgroup; the workgroup sums the pairs of each slice
-// its range touches in LDS bins (W groups) and flushes the bins into the
-// shared accumulators before it moves to the next slice.
+// Partitioned form, pass 3: the slice-ordered pairs (2-byte group offsets
+// inside their slice, 4-byte values) are cut into one contiguous share per
+// workgroup, balanced over pairs plus the cost of flushing each slice; the
+// workgroup sums the pairs of each slice its share touches in LDS bins (W
+// groups) and flushes the bins into the shared accumulators before it moves
+// to the next slice.
 // ---------------------------------------------------------------------------
-constexpr int kSliceVecs = 4;
+constexpr int kSliceVecs = 2;  // 8-pair vectors per lane per batch
 
 struct PairVec {
-  i32x4 k, v;
+  i32x4 l;       // 8 group offsets, 2 bytes each
+  i32x4 v0, v1;  // their 8 values
 };
 
 __device__ __forceinline__ void slice_flush(uint64_t *bsum, uint32_t *bcnt, int32_t slen, int64_t sbase,
@@ -395,7 +398,7 @@ __device__ __forceinline__ void slice_flush(uint64_t *bsum, uint32_t *bcnt, int3
 }
 
 __global__ __launch_bounds__(kGroupThreads) void group_slice_kernel(
-    const int32_t *__restrict__ keys, const int32_t *__restrict__ vals, const uint32_t *__restrict__ slice_off,
+    const uint16_t *__restrict__ locals, const int32_t *__restrict__ vals, const uint32_t *__restrict__ slice_off,
     int32_t P, int32_t m, int32_t t, int32_t wshift, uint64_t *__restrict__ acc_sum, uint64_t *__restrict__ acc_cnt) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int32_t W = 1 << wshift;
@@ -408,44 +411,35 @@ __global__ __launch_bounds__(kGroupThreads) void group_slice_kernel(
   }
   for (int p = threadIdx.x; p <= P; p += blockDim.x) soff[p] = slice_off[p];
   __syncthreads();
-  const uint32_t total = soff[P];
-  const uint32_t lo = (uint32_t)((uint64_t)total * blockIdx.x / gridDim.x);
-  const uint32_t hi = (uint32_t)((uint64_t)total * (blockIdx.x + 1) / gridDim.x);
-  int32_t p = 0;
-  {  // last slice that starts at or before lo
-    int32_t a = 0, b = P;
-    while (b - a > 1) {
-      const int32_t mid = (a + b) >> 1;
-      if (soff[mid] <= lo) a = mid;
-      else b = mid;
-    }
-    p = a;
-  }
-  const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys);
+  uint32_t lo, hi;
+  balanced_share(soff, P, 2u * (uint32_t)W, blockIdx.x, gridDim.x, &lo, &hi);
+  int32_t p = lo < hi ? slice_of_item(soff, P, lo) : P;
+  const i32x4 *vl = reinterpret_cast<const i32x4 *>(locals);
   const i32x4 *vv = reinterpret_cast<const i32x4 *>(vals);
+  auto add = [&](uint32_t local, int32_t v) {  // local < W by construction
+    lds_add_u64(&bsum[local], (uint64_t)(int64_t)v);
+    lds_add_u32(&bcnt[local], 1u);
+  };
   for (uint32_t at = lo; at < hi; ++p) {
     const uint32_t end = soff[p + 1] < hi ? soff[p + 1] : hi;
     if (end <= at) continue;
     const int64_t sbase = (int64_t)t + ((int64_t)p << wshift);
     const int32_t slen = (int32_t)((int64_t)m - sbase < W ? (int64_t)m - sbase : W);
-    const uint32_t smax = (uint32_t)slen - 1;
-    auto add = [&](int32_t g, int32_t v) {
-      uint32_t local = (uint32_t)(g - (int32_t)sbase);
-      local = local < smax ? local : smax;
-      lds_add_u64(&bsum[local], (uint64_t)(int64_t)v);
-      lds_add_u32(&bcnt[local], 1u);
-    };
-    walk_items<kSliceVecs, kGroupThreads, PairVec>(
-        at, end, [&](uint32_t i) { add(keys[i], vals[i]); },
-        [&](uint32_t vi) { return PairVec{load_stream4(vk + vi), load_stream4(vv + vi)}; },
+    walk_items<8, kSliceVecs, kGroupThreads, PairVec>(
+        at, end, [&](uint32_t i) { add(locals[i], vals[i]); },
+        [&](uint32_t vi) { return PairVec{load_stream4(vl + vi), load_stream4(vv + 2 * vi), load_stream4(vv + 2 * vi + 1)}; },
         [&](const PairVec(&x)[kSliceVecs], const bool(&valid)[kSliceVecs]) {
 #pragma unroll
           for (int u = 0; u < kSliceVecs; ++u) {
             if (!valid[u]) continue;
-            add(x[u].k.x, x[u].v.x);
-            add(x[u].k.y, x[u].v.y);
-            add(x[u].k.z, x[u].v.z);
-            add(x[u].k.w, x[u].v.w);
+            const uint32_t d[4] = {(uint32_t)x[u].l.x, (uint32_t)x[u].l.y, (uint32_t)x[u].l.z, (uint32_t)x[u].l.w};
+            const int32_t v[8] = {x[u].v0.x, x[u].v0.y, x[u].v0.z, x[u].v0.w,
+                                  x[u].v1.x, x[u].v1.y, x[u].v1.z, x[u].v1.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              add(d[j] & 0xFFFFu, v[2 * j]);
+              add(d[j] >> 16, v[2 * j + 1]);
+            }
           }
         });
     __syncthreads();
@@ -513,8 +507,9 @@ size_t group_partition_bytes(const GroupPlan &pl) {
   auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const int32_t P = pl.slices > 0 ? pl.slices : 1;
   return 2 * r((size_t)pl.blocks * pl.seg_cap * 4)  // cold segments (keys, values)
-         + 2 * r((size_t)pl.round * 4 + 16)         // slice-ordered pairs
-         + r((size_t)P * pl.blocks * 4) + r((size_t)P * 4) + r(4) + r((size_t)pl.blocks * 4) + 2 * r((size_t)(P + 1) * 4);
+         + r((size_t)pl.round * 2 + 16)             // slice-ordered group offsets (2 bytes)
+         + r((size_t)pl.round * 4 + 16)             // slice-ordered values
+         + r((size_t)P * pl.blocks * 4) + r((size_t)P * 4) + r(4) + r((size_t)pl.blocks * 4) + r((size_t)(P + 1) * 4);
 }
 
 hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact, int32_t n_groups, GroupMode mode,
@@ -576,8 +571,8 @@ hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact
       ws += r((size_t)pl.blocks * pl.seg_cap * 4);
       int32_t *seg_v = (int32_t *)ws;
       ws += r((size_t)pl.blocks * pl.seg_cap * 4);
-      int32_t *items_k = (int32_t *)ws;
-      ws += r((size_t)pl.round * 4 + 16);
+      uint16_t *items_k = (uint16_t *)ws;
+      ws += r((size_t)pl.round * 2 + 16);
       int32_t *items_v = (int32_t *)ws;
       ws += r((size_t)pl.round * 4 + 16);
       SliceTables tab;
@@ -590,8 +585,6 @@ hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact
       tab.seg_count = (uint32_t *)ws;
       ws += r((size_t)pl.blocks * 4);
       tab.slice_off = (uint32_t *)ws;
-      ws += r((size_t)(pl.slices + 1) * 4);
-      tab.unit_start = (uint32_t *)ws;
       const size_t lds1 = group_lds_bytes(t) + (size_t)kWave * 12 + (size_t)(pl.slices + kWave + 4) * 4;
       const size_t lds3 = ((size_t)12 << pl.wshift) + (size_t)(pl.slices + 1) * 4;
       allow_lds(group_split_kernel, lds1);

@@ -405,61 +405,65 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Partitioned form, pass 3: the slice-ordered cold keys are cut evenly into
-// one contiguous range per workgroup; the workgroup walks the slices its range
-// touches, copies each into LDS when its share of the slice is large enough
-// to pay for the copy, and gathers the words from global memory otherwise.
+// Partitioned form, pass 3: the slice-ordered cold items (2-byte offsets
+// inside their slice) are cut into one contiguous share per workgroup,
+// balanced over items plus the cost of copying each slice; the workgroup
+// walks the slices its share touches, copies each into LDS when its part of
+// the slice is large enough to pay for the copy, and gathers the words from
+// global memory otherwise.
 // ---------------------------------------------------------------------------
-constexpr int kSliceVecs = 4;  // 16-byte key vectors per lane per batch
+constexpr int kSliceVecs = 2;  // 16-byte vectors (8 items each) per lane per batch
 
-template <int GROUPS, bool DENSE>
+template <bool DENSE>
 struct SliceLookup {
-  const uint32_t *slice;  // LDS copy of rows [sbase, sbase + smax]
-  int32_t sbase;
-  uint32_t smax;
+  const uint32_t *slice;  // LDS copy of rows [sbase, sbase + W)
+  uint32_t sbase;
   rsrc_t words;
-  __device__ __forceinline__ uint32_t operator()(uint32_t k) const {
-    if (DENSE) {
-      const uint32_t local = k - (uint32_t)sbase;
-      return slice[local < smax ? local : smax];
-    }
-    return buffer_load_record(words, (int32_t)k, 0, 0, 0);
+  __device__ __forceinline__ uint32_t operator()(uint32_t local) const {
+    if (DENSE) return slice[local];
+    return buffer_load_record(words, (int32_t)(sbase + local), 0, 0, 0);
   }
 };
 
 template <int GROUPS, int V, class L>
 __device__ __forceinline__ void join_slice_batch(JoinCtx<GROUPS> &c, const L &look, const i32x4 (&x)[V],
                                                  const bool (&valid)[V]) {
-  uint32_t k[4 * V], w[4 * V];
+  uint32_t l[8 * V], w[8 * V];
 #pragma unroll
   for (int u = 0; u < V; ++u) {
-    k[4 * u] = (uint32_t)x[u].x, k[4 * u + 1] = (uint32_t)x[u].y;
-    k[4 * u + 2] = (uint32_t)x[u].z, k[4 * u + 3] = (uint32_t)x[u].w;
+    const uint32_t d[4] = {(uint32_t)x[u].x, (uint32_t)x[u].y, (uint32_t)x[u].z, (uint32_t)x[u].w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      l[8 * u + 2 * j] = d[j] & 0xFFFFu;
+      l[8 * u + 2 * j + 1] = d[j] >> 16;
+    }
   }
 #pragma unroll
-  for (int i = 0; i < 4 * V; ++i) {
-    w[i] = valid[i / 4] ? look(k[i]) : kValid;
-  }
+  for (int i = 0; i < 8 * V; ++i) w[i] = valid[i / 8] ? look(l[i]) : kValid;
   uint32_t all = kValid;
 #pragma unroll
-  for (int i = 0; i < 4 * V; ++i) {
+  for (int i = 0; i < 8 * V; ++i) {
     all &= w[i];
     join_add(c, w[i]);
   }
-  if (__builtin_expect(!(all & kValid), 0)) join_slow_batch(c, w, k);
+  if (__builtin_expect(!(all & kValid), 0)) {
+#pragma unroll
+    for (int i = 0; i < 8 * V; ++i) l[i] += look.sbase;  // back to dimension rows for the slow path
+    join_slow_batch(c, w, l);
+  }
 }
 
 template <int GROUPS, class L>
-__device__ __forceinline__ void join_slice_range(JoinCtx<GROUPS> &c, const L &look, const int32_t *__restrict__ items,
+__device__ __forceinline__ void join_slice_range(JoinCtx<GROUPS> &c, const L &look, const uint16_t *__restrict__ items,
                                                  uint32_t lo, uint32_t hi) {
   const i32x4 *vk = reinterpret_cast<const i32x4 *>(items);
-  walk_items<kSliceVecs, kJoinThreads, i32x4>(
+  walk_items<8, kSliceVecs, kJoinThreads, i32x4>(
       lo, hi,
       [&](uint32_t i) {
-        const uint32_t k = (uint32_t)items[i];
-        const uint32_t w = look(k);
+        const uint32_t local = items[i];
+        const uint32_t w = look(local);
         join_add(c, w);
-        if (!w) join_slow(c, k);
+        if (!w) join_slow(c, look.sbase + local);
       },
       [&](uint32_t vi) { return load_stream4(vk + vi); },
       [&](const i32x4(&x)[kSliceVecs], const bool(&valid)[kSliceVecs]) {
@@ -469,7 +473,7 @@ __device__ __forceinline__ void join_slice_range(JoinCtx<GROUPS> &c, const L &lo
 
 template <int GROUPS>
 __global__ __launch_bounds__(kJoinThreads) void join_slice_kernel(
-    const int32_t *__restrict__ items, const uint32_t *__restrict__ slice_off, int32_t P,
+    const uint16_t *__restrict__ items, const uint32_t *__restrict__ slice_off, int32_t P,
     const uint32_t *__restrict__ words, int32_t n_rows, int32_t t, int32_t wshift, const int32_t *__restrict__ price,
     const int8_t *__restrict__ cat, int32_t cat_lt, int64_t *__restrict__ out_sum, int64_t *__restrict__ out_cnt,
     int32_t *flag) {
@@ -483,33 +487,23 @@ __global__ __launch_bounds__(kJoinThreads) void join_slice_kernel(
   for (int p = threadIdx.x; p <= P; p += blockDim.x) soff[p] = slice_off[p];
   __syncthreads();
   const rsrc_t wr = record_buffer(words, (uint32_t)n_rows);
-  const uint32_t total = soff[P];
-  const uint32_t lo = (uint32_t)((uint64_t)total * blockIdx.x / gridDim.x);
-  const uint32_t hi = (uint32_t)((uint64_t)total * (blockIdx.x + 1) / gridDim.x);
-  // first slice that ends after lo
-  int32_t p = 0;
-  {
-    int32_t a = 0, b = P;  // soff[a] <= lo < soff[b] for non-empty ranges
-    while (b - a > 1) {
-      const int32_t m = (a + b) >> 1;
-      if (soff[m] <= lo) a = m;
-      else b = m;
-    }
-    p = a;
-  }
+  // copying a slice moves 4 W bytes, as much as 2 W items of 2 bytes
+  uint32_t lo, hi;
+  balanced_share(soff, P, 2u * (uint32_t)W, blockIdx.x, gridDim.x, &lo, &hi);
+  int32_t p = lo < hi ? slice_of_item(soff, P, lo) : P;
   for (uint32_t at = lo; at < hi; ++p) {
     const uint32_t end = soff[p + 1] < hi ? soff[p + 1] : hi;
     if (end <= at) continue;
     const int64_t sbase = (int64_t)t + ((int64_t)p << wshift);
     const int32_t slen = (int32_t)((int64_t)n_rows - sbase < W ? (int64_t)n_rows - sbase : W);
-    if (end - at >= (uint32_t)(W >> 3)) {  // enough keys to pay for copying the slice
+    if (end - at >= (uint32_t)(W >> 3)) {  // enough items to pay for copying the slice
       __syncthreads();
       stage_words(slice, words, sbase, slen);
       __syncthreads();
-      const SliceLookup<GROUPS, true> look{slice, (int32_t)sbase, (uint32_t)slen - 1, wr};
+      const SliceLookup<true> look{slice, (uint32_t)sbase, wr};
       join_slice_range(c, look, items, at, end);
     } else {
-      const SliceLookup<GROUPS, false> look{slice, (int32_t)sbase, (uint32_t)slen - 1, wr};
+      const SliceLookup<false> look{slice, (uint32_t)sbase, wr};
       join_slice_range(c, look, items, at, end);
     }
     at = end;
@@ -565,9 +559,9 @@ size_t join_partition_bytes(const JoinPlan &pl) {
   auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const int32_t P = pl.slices > 0 ? pl.slices : 1;
   return r((size_t)pl.blocks * pl.seg_cap * 4)       // cold segments
-         + r((size_t)pl.round * 4 + 16)              // slice-ordered keys
+         + r((size_t)pl.round * 2 + 16)              // slice-ordered items (2-byte offsets)
          + r((size_t)P * pl.blocks * 4)              // (slice, block) counts
-         + r((size_t)P * 4) + r(4) + r((size_t)pl.blocks * 4) + 2 * r((size_t)(P + 1) * 4);
+         + r((size_t)P * 4) + r(4) + r((size_t)pl.blocks * 4) + r((size_t)(P + 1) * 4);
 }
 
 hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price, const int8_t *cat, int32_t n_rows,
@@ -620,8 +614,8 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
   char *ws = (char *)part_ws;
   int32_t *seg = (int32_t *)ws;
   ws += r((size_t)pl.blocks * pl.seg_cap * 4);
-  int32_t *items = (int32_t *)ws;
-  ws += r((size_t)pl.round * 4 + 16);
+  uint16_t *items = (uint16_t *)ws;
+  ws += r((size_t)pl.round * 2 + 16);
   SliceTables tab;
   tab.hist = (uint32_t *)ws;
   ws += r((size_t)pl.slices * pl.blocks * 4);
@@ -632,8 +626,6 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
   tab.seg_count = (uint32_t *)ws;
   ws += r((size_t)pl.blocks * 4);
   tab.slice_off = (uint32_t *)ws;
-  ws += r((size_t)(pl.slices + 1) * 4);
-  tab.unit_start = (uint32_t *)ws;
 
   const size_t lds1 = join_lds_bytes(groups, t) + (size_t)(pl.slices + kWave + 4) * 4;
   const size_t lds3 = (groups == 16 ? (size_t)kJoinBins * kWave * 8 : 0) + ((size_t)4 << pl.wshift) +

@@ -34,12 +34,13 @@ hipError_t launch_recode(const int32_t *keys, int64_t n, const int32_t *rank, in
 // ---- prefix sums and cold-item partitioning ----
 struct SliceTables;
 hipError_t launch_exclusive_scan(uint32_t *a, int64_t n, uint32_t *total, hipStream_t s);
-// Scan of the (slice, block) counts and the slice/unit tables.
+// Scan of the (slice, block) counts and the slice table.
 hipError_t launch_partition_plan(const SliceTables &tab, int32_t P, int32_t B, hipStream_t s);
-// Move every block's cold items into slice order.
+// Move every block's cold items into slice order, as 2-byte offsets inside
+// their slice (plus the values when seg_vals is given).
 hipError_t launch_partition_scatter(const SliceTables &tab, int32_t P, int32_t B, const int32_t *seg_keys,
                                     const int32_t *seg_vals, int64_t seg_cap, int32_t t, int32_t wshift,
-                                    int32_t *out_keys, int32_t *out_vals, hipStream_t s);
+                                    uint16_t *out_local, int32_t *out_vals, hipStream_t s);
 
 // ---- queries (Section 4) ----
 constexpr int kJoinThreads = 1024;

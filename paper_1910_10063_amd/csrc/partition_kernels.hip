@@ -85,86 +85,77 @@ __global__ __launch_bounds__(kRowScanThreads) void row_scan_kernel(uint32_t *__r
 
 // ---------------------------------------------------------------------------
 // Slice plan, step 2 (one workgroup, P <= kMaxSlices): the first item of every
-// slice (exclusive scan of the row totals), the total, and the first unit of
-// every slice (units of at most kUnitItems).
+// slice (exclusive scan of the row totals) and the total.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kMaxSlices) void slice_plan_kernel(const uint32_t *__restrict__ row_total, int32_t P,
                                                                 uint32_t *__restrict__ total,
-                                                                uint32_t *__restrict__ slice_off,
-                                                                uint32_t *__restrict__ unit_start) {
-  __shared__ uint32_t wave_off[kMaxSlices / kWave][2];
+                                                                uint32_t *__restrict__ slice_off) {
+  __shared__ uint32_t wave_off[kMaxSlices / kWave];
   const int p = threadIdx.x, lane = lane_id(), wave = p / kWave;
   const uint32_t cnt = p < P ? row_total[p] : 0u;
-  const uint32_t units = (cnt + kUnitItems - 1) / kUnitItems;
   const uint32_t ic = wave_inclusive_scan(cnt);
-  const uint32_t iu = wave_inclusive_scan(units);
-  if (lane == kWave - 1) {
-    wave_off[wave][0] = ic;
-    wave_off[wave][1] = iu;
-  }
+  if (lane == kWave - 1) wave_off[wave] = ic;
   __syncthreads();
   if (wave == 0) {
-    const uint32_t wc = lane < kMaxSlices / kWave ? wave_off[lane][0] : 0u;
-    const uint32_t wu = lane < kMaxSlices / kWave ? wave_off[lane][1] : 0u;
+    const uint32_t wc = lane < kMaxSlices / kWave ? wave_off[lane] : 0u;
     const uint32_t xc = wave_inclusive_scan(wc);
-    const uint32_t xu = wave_inclusive_scan(wu);
-    if (lane < kMaxSlices / kWave) {
-      wave_off[lane][0] = xc - wc;
-      wave_off[lane][1] = xu - wu;
-    }
+    if (lane < kMaxSlices / kWave) wave_off[lane] = xc - wc;
   }
   __syncthreads();
-  const uint32_t first_item = wave_off[wave][0] + ic - cnt;
-  const uint32_t first_unit = wave_off[wave][1] + iu - units;
-  if (p < P) {
-    slice_off[p] = first_item;
-    unit_start[p] = first_unit;
-  }
+  const uint32_t first_item = wave_off[wave] + ic - cnt;
+  if (p < P) slice_off[p] = first_item;
   if (p == P - 1) {
     slice_off[P] = first_item + cnt;
-    unit_start[P] = first_unit + units;
     *total = first_item + cnt;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Scatter: block b moves the cold items of its segment to their slice-order
-// positions.  Items are first sorted by slice inside LDS, one tile at a time,
-// so that consecutive lanes write consecutive slots (a handful of cache lines
-// per store instead of one per lane).
+// positions, as 2-byte offsets inside their slice ((k - t) & (W - 1)) plus the
+// value when there is one.  Items are first sorted by slice inside LDS, one
+// tile at a time, so that consecutive lanes write consecutive slots.
 // ---------------------------------------------------------------------------
 constexpr int kScatterThreads = 1024;
-constexpr int kScatterPer = 8;
+constexpr int kScatterVecs = 4;                          // 16-byte loads per thread per tile
+constexpr int kScatterPer = 4 * kScatterVecs;            // items per thread per tile
 constexpr int kScatterTile = kScatterThreads * kScatterPer;
+
+size_t scatter_lds_bytes(bool pairs) { return (size_t)kScatterTile * 4 * (pairs ? 2 : 1); }
 
 template <bool PAIRS>
 __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
     const int32_t *__restrict__ seg_keys, const int32_t *__restrict__ seg_vals, int64_t seg_cap,
     const uint32_t *__restrict__ seg_count, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ slice_off,
-    int32_t P, int32_t t, int32_t wshift, int32_t *__restrict__ out_keys, int32_t *__restrict__ out_vals) {
+    int32_t P, int32_t t, int32_t wshift, uint16_t *__restrict__ out_local, int32_t *__restrict__ out_vals) {
   __shared__ uint32_t run[kMaxSlices];    // next global slot of every slice for this block
   __shared__ uint32_t start[kMaxSlices];  // tile histogram, then first local slot of every slice
   __shared__ uint32_t wave_off[kScatterThreads / kWave];
-  __shared__ int32_t skey[kScatterTile];
-  __shared__ int32_t sval[PAIRS ? kScatterTile : 1];
+  extern __shared__ __align__(16) unsigned char smem[];
+  int32_t *skey = reinterpret_cast<int32_t *>(smem);
+  int32_t *sval = skey + kScatterTile;  // PAIRS only
   const int b = blockIdx.x, B = gridDim.x, tid = threadIdx.x;
   for (int p = tid; p < P; p += blockDim.x) run[p] = slice_off[p] + hist[(int64_t)p * B + b];
   const uint32_t cnt = seg_count[b];
-  const int32_t *sk = seg_keys + (int64_t)b * seg_cap;
-  const int32_t *sv = PAIRS ? seg_vals + (int64_t)b * seg_cap : nullptr;
+  // segments start 16-byte aligned and hold a multiple of 4 slots, so every
+  // vector that starts below cnt lies inside the segment
+  const i32x4 *sk = reinterpret_cast<const i32x4 *>(seg_keys + (int64_t)b * seg_cap);
+  const i32x4 *sv = reinterpret_cast<const i32x4 *>(PAIRS ? seg_vals + (int64_t)b * seg_cap : seg_keys);
+  const uint32_t wmask = (1u << wshift) - 1u;
   auto slice_of = [&](int32_t k) -> uint32_t {
     const uint32_t p = (uint32_t)(k - t) >> wshift;
     return p < (uint32_t)P ? p : (uint32_t)P - 1;  // pass 1 only writes ids in [t, t + P * W)
   };
-  // The next tile's items are loaded into registers while the current tile is
-  // sorted and written.
-  int32_t k[kScatterPer], v[kScatterPer], kn[kScatterPer], vn[kScatterPer];
-  auto load_tile = [&](int32_t(&kk)[kScatterPer], int32_t(&vv)[kScatterPer], uint32_t base) {
+  // The next tile is loaded into registers while the current tile is sorted
+  // and written.
+  i32x4 k[kScatterVecs], v[kScatterVecs], kn[kScatterVecs], vn[kScatterVecs];
+  auto load_tile = [&](i32x4(&kk)[kScatterVecs], i32x4(&vv)[kScatterVecs], uint32_t base) {
 #pragma unroll
-    for (int i = 0; i < kScatterPer; ++i) {
-      const uint32_t j = base + (uint32_t)i * kScatterThreads + tid;
-      kk[i] = j < cnt ? load_stream1(sk + j) : 0;
-      if (PAIRS) vv[i] = j < cnt ? load_stream1(sv + j) : 0;
+    for (int u = 0; u < kScatterVecs; ++u) {
+      const uint32_t vi = base / 4 + (uint32_t)u * kScatterThreads + tid;
+      const bool ok = 4 * vi < cnt;
+      kk[u] = ok ? load_stream4(sk + vi) : i32x4{0, 0, 0, 0};
+      if (PAIRS) vv[u] = ok ? load_stream4(sv + vi) : i32x4{0, 0, 0, 0};
     }
   };
   if (cnt) load_tile(k, v, 0);
@@ -174,9 +165,13 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
     __syncthreads();
     uint32_t rk[kScatterPer];
 #pragma unroll
-    for (int i = 0; i < kScatterPer; ++i) {
-      const uint32_t j = (uint32_t)i * kScatterThreads + tid;
-      rk[i] = j < n ? atomicAdd(&start[slice_of(k[i])], 1u) : 0u;  // rank among this tile's items of the slice
+    for (int u = 0; u < kScatterVecs; ++u) {
+      const int32_t kv[4] = {k[u].x, k[u].y, k[u].z, k[u].w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t i = 4 * ((uint32_t)u * kScatterThreads + tid) + j;  // item within the tile
+        rk[4 * u + j] = i < n ? atomicAdd(&start[slice_of(kv[j])], 1u) : 0u;  // rank among the tile's items of the slice
+      }
     }
     if (base + kScatterTile < cnt) load_tile(kn, vn, base + kScatterTile);
     __syncthreads();
@@ -204,12 +199,17 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
     if (tid < P) start[tid] = wave_off[tid / kWave] + incl - c;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kScatterPer; ++i) {
-      const uint32_t j = (uint32_t)i * kScatterThreads + tid;
-      if (j < n) {
-        const uint32_t pos = start[slice_of(k[i])] + rk[i];
-        skey[pos] = k[i];
-        if (PAIRS) sval[pos] = v[i];
+    for (int u = 0; u < kScatterVecs; ++u) {
+      const int32_t kv[4] = {k[u].x, k[u].y, k[u].z, k[u].w};
+      const int32_t vv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t i = 4 * ((uint32_t)u * kScatterThreads + tid) + j;
+        if (i < n) {
+          const uint32_t pos = start[slice_of(kv[j])] + rk[4 * u + j];
+          skey[pos] = kv[j];
+          if (PAIRS) sval[pos] = vv[j];
+        }
       }
     }
     __syncthreads();
@@ -217,15 +217,15 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
       const int32_t kk = skey[j];
       const uint32_t p = slice_of(kk);
       const uint32_t g = run[p] + (j - start[p]);
-      out_keys[g] = kk;
+      out_local[g] = (uint16_t)((uint32_t)(kk - t) & wmask);
       if (PAIRS) out_vals[g] = sval[j];
     }
     __syncthreads();
     if (tid < P) run[tid] += c;
 #pragma unroll
-    for (int i = 0; i < kScatterPer; ++i) {
-      k[i] = kn[i];
-      if (PAIRS) v[i] = vn[i];
+    for (int u = 0; u < kScatterVecs; ++u) {
+      k[u] = kn[u];
+      if (PAIRS) v[u] = vn[u];
     }
   }
 }
@@ -243,20 +243,26 @@ hipError_t launch_partition_plan(const SliceTables &tab, int32_t P, int32_t B, h
                      tab.row_total);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(kMaxSlices), 0, s, tab.row_total, P, tab.total, tab.slice_off,
-                     tab.unit_start);
+  hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(kMaxSlices), 0, s, tab.row_total, P, tab.total, tab.slice_off);
   return hipGetLastError();
 }
 
 hipError_t launch_partition_scatter(const SliceTables &tab, int32_t P, int32_t B, const int32_t *seg_keys,
                                     const int32_t *seg_vals, int64_t seg_cap, int32_t t, int32_t wshift,
-                                    int32_t *out_keys, int32_t *out_vals, hipStream_t s) {
-  if (seg_vals)
-    hipLaunchKernelGGL(scatter_kernel<true>, dim3(B), dim3(kScatterThreads), 0, s, seg_keys, seg_vals, seg_cap,
-                       tab.seg_count, tab.hist, tab.slice_off, P, t, wshift, out_keys, out_vals);
-  else
-    hipLaunchKernelGGL(scatter_kernel<false>, dim3(B), dim3(kScatterThreads), 0, s, seg_keys, seg_vals, seg_cap,
-                       tab.seg_count, tab.hist, tab.slice_off, P, t, wshift, out_keys, out_vals);
+                                    uint16_t *out_local, int32_t *out_vals, hipStream_t s) {
+  if (seg_vals) {
+    const size_t lds = scatter_lds_bytes(true);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(scatter_kernel<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(scatter_kernel<true>, dim3(B), dim3(kScatterThreads), lds, s, seg_keys, seg_vals, seg_cap,
+                       tab.seg_count, tab.hist, tab.slice_off, P, t, wshift, out_local, out_vals);
+  } else {
+    const size_t lds = scatter_lds_bytes(false);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(scatter_kernel<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(scatter_kernel<false>, dim3(B), dim3(kScatterThreads), lds, s, seg_keys, seg_vals, seg_cap,
+                       tab.seg_count, tab.hist, tab.slice_off, P, t, wshift, out_local, out_vals);
+  }
   return hipGetLastError();
 }
 

@@ -65,11 +65,10 @@ __device__ __forceinline__ rsrc_t record_buffer(const void *base, uint32_t num_r
 // ids; slice p is small enough to live in LDS.  Pass 1 writes each block's
 // cold items into its own segment and counts them per slice; a scan turns the
 // (slice, block) counts into offsets; a scatter puts the items in slice
-// order; pass 3 cuts every slice into units of at most kUnitItems items and
-// resolves each unit from an LDS copy of its slice.
+// order as 2-byte offsets inside their slice (W <= 2^16); pass 3 resolves
+// the items of each slice from an LDS copy of it.
 // ---------------------------------------------------------------------------
 constexpr int kMaxSlices = 1024;
-constexpr uint32_t kUnitItems = 1u << 16;
 
 struct SliceTables {       // in global memory (workspace)
   uint32_t *hist;          // [P][B]: cold items of block b in slice p, then prefixes within the slice
@@ -77,7 +76,6 @@ struct SliceTables {       // in global memory (workspace)
   uint32_t *total;         // [1]: number of cold items
   uint32_t *seg_count;     // [B]: cold items written by block b
   uint32_t *slice_off;     // [P + 1]: first item of slice p in slice order
-  uint32_t *unit_start;    // [P + 1]: first unit of slice p
 };
 
 
@@ -137,25 +135,27 @@ __device__ __forceinline__ void cold_append(const ColdSink &o, const uint32_t (&
 }
 
 // ---------------------------------------------------------------------------
-// Items [lo, hi) of 4-byte item arrays (16-byte aligned at item 0) visited by
-// a workgroup of THREADS threads: the at most 3 items before the first 16-byte
-// boundary (threads 0-2) and after the last one (threads 64-66) one at a time,
-// the rest in batches of V 16-byte vectors per thread, the next batch loaded
-// while the current one is processed, then one guarded partial batch.
+// Items [lo, hi) of item arrays that hold IPV items per 16-byte vector (and
+// start 16-byte aligned at item 0), visited by a workgroup of THREADS
+// threads: the items before the first vector boundary (threads 0..) and after
+// the last one (threads 64..) one at a time, the rest in batches of V vectors
+// per thread, the next batch loaded while the current one is processed, then
+// one guarded partial batch.
 //   one(i)                       item i
-//   load(vi) -> T                vector vi (items 4 vi .. 4 vi + 3)
+//   load(vi) -> T                vector vi (items IPV vi .. IPV vi + IPV - 1)
 //   batch(const T (&)[V], const bool (&valid)[V])
 // ---------------------------------------------------------------------------
-template <int V, int THREADS, class T, class One, class Load, class Batch>
+template <int IPV, int V, int THREADS, class T, class One, class Load, class Batch>
 __device__ __forceinline__ void walk_items(uint32_t lo, uint32_t hi, One one, Load load, Batch batch) {
-  const uint32_t al = (lo + 3) & ~3u;
+  static_assert(IPV <= kWave, "head and tail items are taken by one wave each");
+  const uint32_t al = (lo + IPV - 1) / IPV * IPV;
   if (al >= hi) {
     if (threadIdx.x < hi - lo) one(lo + threadIdx.x);
     return;
   }
   if (threadIdx.x < al - lo) one(lo + threadIdx.x);
-  const uint32_t vb = al >> 2, ve = hi >> 2;
-  if (threadIdx.x >= kWave && threadIdx.x - kWave < hi - 4 * ve) one(4 * ve + threadIdx.x - kWave);
+  const uint32_t vb = al / IPV, ve = hi / IPV;
+  if (threadIdx.x >= kWave && threadIdx.x - kWave < hi - IPV * ve) one(IPV * ve + threadIdx.x - kWave);
 
   constexpr uint32_t kBatch = (uint32_t)V * THREADS;
   const uint32_t full = vb + ((ve - vb) / kBatch) * kBatch;
@@ -191,6 +191,42 @@ __device__ __forceinline__ void walk_items(uint32_t lo, uint32_t hi, One one, Lo
     }
     batch(x, valid);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Share of workgroup b of B in pass 3.  Every slice costs its items plus S
+// item-equivalents for copying or flushing its LDS image; the total cost is
+// cut evenly and each cut is mapped back to an item (cuts inside a slice's
+// fixed cost map to its first item).  soff[0..P] are the slice offsets.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t cost_to_item(const uint32_t *soff, int32_t P, uint32_t S, uint64_t c) {
+  int32_t a = 0, z = P;  // largest p in [0, P] with soff[p] + p * S <= c
+  while (a < z) {
+    const int32_t m = (a + z + 1) >> 1;
+    if ((uint64_t)soff[m] + (uint64_t)m * S <= c) a = m;
+    else z = m - 1;
+  }
+  if (a == P) return soff[P];
+  const uint64_t in = c - ((uint64_t)soff[a] + (uint64_t)a * S);
+  return soff[a] + (in > S ? (uint32_t)(in - S) : 0u);
+}
+
+__device__ __forceinline__ void balanced_share(const uint32_t *soff, int32_t P, uint32_t S, uint32_t b, uint32_t B,
+                                               uint32_t *lo, uint32_t *hi) {
+  const uint64_t total = (uint64_t)soff[P] + (uint64_t)P * S;
+  *lo = cost_to_item(soff, P, S, total * b / B);
+  *hi = cost_to_item(soff, P, S, total * (b + 1) / B);
+}
+
+// Last slice that starts at or before item i (P >= 1).
+__device__ __forceinline__ int32_t slice_of_item(const uint32_t *soff, int32_t P, uint32_t i) {
+  int32_t a = 0, z = P - 1;
+  while (a < z) {
+    const int32_t m = (a + z + 1) >> 1;
+    if (soff[m] <= i) a = m;
+    else z = m - 1;
+  }
+  return a;
 }
 
 }  // namespace skew
