@@ -30,7 +30,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "fact tuples/s and % of HBM roofline, skew layout vs identity layout (bit-exact)"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "join_kernel_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "join_split_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1910_10063_amd", "csrc", f)
                   for f in ("join_kernels.hip", "partition_kernels.hip", "query_common.h", "device_common.h",
                             "kernels.h")]
@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="headline query only (for profiler runs)")
     ap.add_argument("--with-group", action="store_true", help="run the group-by workload even with --no-extras")
+    ap.add_argument("--skew-only", action="store_true",
+                    help="skip the identity-layout query (profiler runs: one kernel name per stage)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (reference for profiler byte counters)")
     args = ap.parse_args()
@@ -142,10 +144,12 @@ def main():
     log("skew-layout query (timed steps)")
     ms_skew = timed(query(Cp, pp, cp, t_hot), K, WU, stream)
     skew_res = (out_s.cpu().numpy().copy(), out_c.cpu().numpy().copy())
-    log("identity-layout query")
-    ms_ident = timed(query(C, price, cat, 0), K, WU, stream)
-    ident_res = (out_s.cpu().numpy().copy(), out_c.cpu().numpy().copy())
-    agree = bool((skew_res[0] == ident_res[0]).all() and (skew_res[1] == ident_res[1]).all())
+    ms_ident, agree = None, None
+    if not args.skew_only:
+        log("identity-layout query")
+        ms_ident = timed(query(C, price, cat, 0), K, WU, stream)
+        ident_res = (out_s.cpu().numpy().copy(), out_c.cpu().numpy().copy())
+        agree = bool((skew_res[0] == ident_res[0]).all() and (skew_res[1] == ident_res[1]).all())
 
     # ---- per-stage times from HIP events recorded by the library on this stream
     KP = max(K // 2, 3)
@@ -154,9 +158,11 @@ def main():
     for _ in range(KP):
         query(Cp, pp, cp, t_hot)()
     st_skew = skew.profile_report()
-    for _ in range(KP):
-        query(C, price, cat, 0)()
-    st_ident = skew.profile_report()
+    st_ident = {}
+    if not args.skew_only:
+        for _ in range(KP):
+            query(C, price, cat, 0)()
+        st_ident = skew.profile_report()
     build()
     st_build = skew.profile_report()
     skew.profile_enable(False)
@@ -166,17 +172,24 @@ def main():
 
     stages_skew = per_query(st_skew, KP)
     stages_ident = per_query(st_ident, KP)
-    # dominant kernel of the skew query; algorithmic bytes per launch: 4 B per fact key it streams
-    # plus 4 B per hot dimension word it stages (pass 1 / single pass), 9 B per dimension row (pack)
+    # dominant kernel of the skew query and its algorithmic bytes per launch (what the stage must move at
+    # least): pass 1 streams 4 B per fact key, stages 4 B per hot dimension word and writes 4 B per cold
+    # key; the scatter reads 4 B and writes 2 B per cold key; pass 3 reads 2 B per cold key and the cold
+    # dimension words once (4 B each); the single pass streams 4 B per key plus the hot words; the pack
+    # reads 5 B and writes 4 B per dimension row.
     dom = max(stages_skew, key=lambda k: stages_skew[k]["ms"])
     launches = stages_skew[dom]["launches"]
     hot_used = min(skew.max_hot_rows(True), N) if t_hot < 0 else min(t_hot, N)
-    if dom in ("join_split", "join_single_pass"):
-        dom_bytes = 4.0 * F / launches + 4.0 * hot_used
-    elif dom == "join_pack":
-        dom_bytes = 9.0 * N
-    else:
-        dom_bytes = 4.0 * F / launches
+    cold = int(cbr[hot_used:].to(torch.int64).sum().item())  # fact keys at or above the threshold
+    per_launch = {
+        "join_split": 4.0 * F / launches + 4.0 * hot_used + 4.0 * cold / launches,
+        "join_single_pass": 4.0 * F / launches + 4.0 * hot_used,
+        "join_scatter": 6.0 * cold / launches,
+        "join_slice": 2.0 * cold / launches + 4.0 * (N - hot_used),
+        "join_pack": 9.0 * N,
+        "join_plan": 0.0,
+    }
+    dom_bytes = per_launch.get(dom, 4.0 * F / launches)
     dom_ms = stages_skew[dom]["ms"] / launches
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     traffic = None
@@ -188,7 +201,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": dom_bytes, "kernel_ms": round(dom_ms, 4),
-                "launches_per_query": launches}
+                "launches_per_query": launches, "cold_fact_keys": cold}
     q_bytes = 4.0 * F + 9.0 * N  # whole query: every fact key once, both dimension columns once
     query_roofline = {"bound": "hbm", "algorithmic_bytes": q_bytes,
                       "achieved": round(q_bytes / (ms_skew * 1e-3) / 1e9, 1),
@@ -215,8 +228,8 @@ def main():
                              "category": W.category_seed(k)}},
         "roofline": roofline,
         "query_roofline": query_roofline,
-        "identity": {"value": F / (ms_ident * 1e-3), "ms_per_step": ms_ident},
-        "speedup_vs_identity": ms_ident / ms_skew,
+        "identity": {"value": F / (ms_ident * 1e-3), "ms_per_step": ms_ident} if ms_ident else None,
+        "speedup_vs_identity": ms_ident / ms_skew if ms_ident else None,
         "stages_ms": {"skew": stages_skew, "identity": stages_ident, "build": per_query(st_build, 1)},
         "build": {"ms": build_ms, "fact_tuples_per_s": F / (build_ms * 1e-3)},
         "layouts_agree": agree,

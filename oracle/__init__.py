@@ -55,6 +55,12 @@ def bind(path: str):
     lib.oracle_group_aggregate.restype = I64
     lib.oracle_build_layout.argtypes = [P, I64, I32, P, P, P, P, P, P, P, P]
     lib.oracle_build_layout.restype = I64
+    lib.oracle_materialize.argtypes = [P, I64, P, I32, P]
+    lib.oracle_materialize.restype = I64
+    lib.oracle_select.argtypes = [P, I64, P, I32, I32, P]
+    lib.oracle_select.restype = I64
+    lib.oracle_heavy_hitters.argtypes = [P, I64, I32, I32, P, P]
+    lib.oracle_heavy_hitters.restype = I32
     return lib
 
 
@@ -140,6 +146,33 @@ def group_aggregate(G, V, n_groups: int):
     c = np.zeros(max(n_groups, 1), dtype=np.int64)[:n_groups]
     invalid = _load().oracle_group_aggregate(_p(G), _p(V), G.size, n_groups, _p(s), _p(c))
     return s, c, int(invalid)
+
+
+def materialize(C, col):
+    """out[j] = col[C[j]] (0 for out-of-range keys); returns (out, invalid)."""
+    C = _c(C, np.int32)
+    col = _c(col, np.int32)
+    out = np.empty(C.size, dtype=np.int32)
+    inv = _load().oracle_materialize(_p(C), C.size, _p(col), col.size, _p(out))
+    return out, int(inv)
+
+
+def select(C, col, lt: int):
+    """Increasing int64 offsets j with col[C[j]] < lt."""
+    C = _c(C, np.int32)
+    col = _c(col, np.int32)
+    out = np.empty(max(C.size, 1), dtype=np.int64)
+    n = _load().oracle_select(_p(C), C.size, _p(col), col.size, int(lt), _p(out))
+    return out[:n].copy()
+
+
+def heavy_hitters(G, n_keys: int, k: int):
+    """(keys, counts) of the k most frequent keys, most frequent first, ties by ascending key."""
+    G = _c(G, np.int32)
+    keys = np.empty(max(min(k, n_keys), 1), dtype=np.int32)
+    counts = np.empty(max(min(k, n_keys), 1), dtype=np.int64)
+    kk = _load().oracle_heavy_hitters(_p(G), G.size, n_keys, int(k), _p(keys), _p(counts))
+    return keys[:kk].copy(), counts[:kk].copy()
 
 
 class Layout:

@@ -172,3 +172,69 @@ int64_t oracle_build_layout(const int32_t *C, int64_t n_fact, int32_t n_keys, co
   free(cnt);
   return invalid;
 }
+
+/*
+ * Materialization (Q1 of Section 1, operator of Section 4.1): the dimension
+ * column gathered through the foreign key, out[j] = col[C[j]].  A key outside
+ * [0, n_rows) materializes 0; the number of such keys is returned.
+ */
+int64_t oracle_materialize(const int32_t *C, int64_t n_fact, const int32_t *col, int32_t n_rows, int32_t *out) {
+  int64_t invalid = 0;
+  for (int64_t j = 0; j < n_fact; ++j) {
+    const int32_t k = C[j];
+    if (k < 0 || k >= n_rows) {
+      out[j] = 0;
+      ++invalid;
+      continue;
+    }
+    out[j] = col[k];
+  }
+  return invalid;
+}
+
+/*
+ * Selection (Q2 of Section 1, operator of Section 4.1): the offsets j of the
+ * fact rows whose dimension row satisfies col[C[j]] < lt, in increasing
+ * order.  (The paper evaluates the dimension predicate once into a bitmap and
+ * tests one bit per fact row; the plain definition tests the predicate.)
+ * Keys outside [0, n_rows) never qualify.  Returns the number of offsets.
+ */
+int64_t oracle_select(const int32_t *C, int64_t n_fact, const int32_t *col, int32_t n_rows, int32_t lt,
+                      int64_t *out) {
+  int64_t n = 0;
+  for (int64_t j = 0; j < n_fact; ++j) {
+    const int32_t k = C[j];
+    if (k < 0 || k >= n_rows) continue;
+    if (col[k] < lt) out[n++] = j;
+  }
+  return n;
+}
+
+/*
+ * Heavy hitters (Q3a of Section 1, Section 4.2.2): the k most frequent keys
+ * of G with their counts, most frequent first, equal counts by ascending key
+ * (k is clamped to n_keys).  Counting every key and sorting is the plain
+ * definition; it is also what the paper's conventional method has to do.
+ * Returns the clamped k.
+ */
+int32_t oracle_heavy_hitters(const int32_t *G, int64_t n_fact, int32_t n_keys, int32_t k, int32_t *keys,
+                             int64_t *counts) {
+  if (k > n_keys) k = n_keys;
+  if (k < 0) k = 0;
+  freq_entry *e = (freq_entry *)malloc(sizeof(freq_entry) * (size_t)(n_keys > 0 ? n_keys : 1));
+  for (int32_t g = 0; g < n_keys; ++g) {
+    e[g].cnt = 0;
+    e[g].key = g;
+  }
+  for (int64_t j = 0; j < n_fact; ++j) {
+    const int32_t g = G[j];
+    if (g >= 0 && g < n_keys) e[g].cnt += 1;
+  }
+  qsort(e, (size_t)n_keys, sizeof(freq_entry), by_decreasing_frequency);
+  for (int32_t r = 0; r < k; ++r) {
+    keys[r] = e[r].key;
+    counts[r] = e[r].cnt;
+  }
+  free(e);
+  return k;
+}

@@ -238,5 +238,101 @@ def pin_stale_layout(orc):
         assert (s == s2).all() and (c == c2).all()
 
 
+# ---------------------------------------------------------------------------
+# Operator variants (Section 4.1): materialization, selection, heavy hitters
+# ---------------------------------------------------------------------------
+def nested_loop_materialize(fact, dim_rows):
+    """For every fact key the value of the dimension row whose key matches (0 if none)."""
+    out = []
+    for fk in fact:
+        v = 0
+        for key, val in dim_rows:
+            if key == fk:
+                v = val
+        out.append(v)
+    return out
+
+
+def pin_materialize(orc, seeds=range(12)):
+    for seed in seeds:
+        rng = np.random.default_rng(300 + seed)
+        n = int(rng.integers(1, 9))
+        f = int(rng.integers(0, 20))
+        col = rng.integers(-2**31, 2**31, n, dtype=np.int64).astype(np.int32)
+        fact = rng.integers(-2, n + 2, f).astype(np.int32)
+        rows = [(int(k), int(col[k])) for k in rng.permutation(n)]
+        out, inv = orc.materialize(fact, col)
+        assert out.tolist() == nested_loop_materialize(fact.tolist(), rows), seed
+        assert inv == int(((fact < 0) | (fact >= n)).sum())
+    # the materialized price column sums to the join's unfiltered SUM(price)
+    rng = np.random.default_rng(31)
+    n, F = 200, 5000
+    price = rng.integers(1, 10001, n).astype(np.int32)
+    cat = rng.integers(0, 16, n).astype(np.int8)
+    fact = rng.integers(0, n, F).astype(np.int32)
+    out, _ = orc.materialize(fact, price)
+    s, _ = orc.fk_join_aggregate(fact, price, cat, 127, False)
+    assert int(out.astype(np.int64).sum()) == int(s[0])
+    # layout invariance: D'[C'[j]] = D[C[j]] for every row (Section 3.2)
+    L = orc.build_layout(fact, n, price, cat)
+    out2, _ = orc.materialize(L.fact_recoded, L.price)
+    assert (out2 == out).all()
+
+
+def pin_select(orc, seeds=range(12)):
+    for seed in seeds:
+        rng = np.random.default_rng(400 + seed)
+        n = int(rng.integers(1, 9))
+        f = int(rng.integers(0, 25))
+        col = rng.integers(-20, 20, n).astype(np.int32)
+        fact = rng.integers(-2, n + 2, f).astype(np.int32)
+        rows = [(int(k), int(col[k])) for k in rng.permutation(n)]
+        for lt in (-100, -3, 0, 7, 100):
+            want = []
+            for j, fk in enumerate(fact.tolist()):
+                for key, val in rows:
+                    if key == fk and val < lt:
+                        want.append(j)
+            assert orc.select(fact, col, lt).tolist() == want, (seed, lt)
+    # the number of selected rows is the join's COUNT(*) under the same filter on category
+    rng = np.random.default_rng(41)
+    n, F = 300, 6000
+    price = rng.integers(1, 10001, n).astype(np.int32)
+    cat = rng.integers(-5, 20, n).astype(np.int8)
+    fact = rng.integers(0, n, F).astype(np.int32)
+    for lt in (-1, 4, 16):
+        _, c = orc.fk_join_aggregate(fact, price, cat, lt, False)
+        assert orc.select(fact, cat.astype(np.int32), lt).size == int(c[0])
+    # layout invariance: the same fact offsets qualify on the skew layout
+    L = orc.build_layout(fact, n, price, cat)
+    assert (orc.select(L.fact_recoded, L.price, 5000) == orc.select(fact, price, 5000)).all()
+
+
+def pin_heavy_hitters(orc, seeds=range(10)):
+    for seed in seeds:
+        rng = np.random.default_rng(500 + seed)
+        n = int(rng.integers(1, 12))
+        f = int(rng.integers(0, 60))
+        G = rng.integers(-1, n + 1, f).astype(np.int32)
+        cnt = {}
+        for g in G.tolist():
+            if 0 <= g < n:
+                cnt[g] = cnt.get(g, 0) + 1
+        order = sorted(range(n), key=lambda g: (-cnt.get(g, 0), g))
+        for k in (0, 1, n // 2, n, n + 3):
+            keys, counts = orc.heavy_hitters(G, n, k)
+            kk = min(k, n)
+            assert keys.tolist() == order[:kk], (seed, k)
+            assert counts.tolist() == [cnt.get(g, 0) for g in order[:kk]], (seed, k)
+    # the top-k are the first k ranks of the permutation index with their frequencies (Section 4.2.2)
+    rng = np.random.default_rng(51)
+    n = 400
+    G = (rng.zipf(1.3, 20000) % n).astype(np.int32)
+    L = orc.build_layout(G, n)
+    keys, counts = orc.heavy_hitters(G, n, 50)
+    assert (keys == L.perm[:50]).all() and (counts == L.counts_by_rank[:50]).all()
+
+
 ALL_PINS = [pin_fk_bruteforce, pin_fk_special_cases, pin_group_bruteforce, pin_layout_bruteforce, pin_fig2,
-            pin_layout_invariants, pin_invariance_all_layouts, pin_stale_layout]
+            pin_layout_invariants, pin_invariance_all_layouts, pin_stale_layout, pin_materialize, pin_select,
+            pin_heavy_hitters]

@@ -25,8 +25,17 @@ MUTANTS = {
     "group_ignored": ("      g = c;\n", "      g = 0;\n"),
     "count_dropped": ("    sum[g] += (int64_t)price[k];\n    count[g] += 1;", "    sum[g] += (int64_t)price[k];"),
     "group_sum_wrong_index": ("sum[g] += (int64_t)V[j];", "sum[g] += (int64_t)V[g];"),
-    "invalid_key_joined": ("    if (k < 0 || k >= n_rows) continue;\n", "    if (k < 0) continue;\n"),
+    "invalid_key_joined": ("    if (k < 0 || k >= n_rows) continue;\n    const int32_t c = category[k];",
+                           "    if (k < 0) continue;\n    const int32_t c = category[k];"),
+    "select_invalid_key": ("    if (k < 0 || k >= n_rows) continue;\n    if (col[k] < lt)", "    if (k < 0) continue;\n    if (col[k] < lt)"),
     "counts_off_by_one": ("    cnt[k] += 1;\n", "    cnt[k] += (k == 0) ? 2 : 1;\n"),
+    "materialize_shifted": ("    out[j] = col[k];\n", "    out[j] = col[k > 0 ? k - 1 : k];\n"),
+    "materialize_invalid_kept": ("      out[j] = 0;\n      ++invalid;", "      out[j] = k;\n      ++invalid;"),
+    "select_le": ("    if (col[k] < lt) out[n++] = j;", "    if (col[k] <= lt) out[n++] = j;"),
+    "select_key_not_offset": ("    if (col[k] < lt) out[n++] = j;", "    if (col[k] < lt) out[n++] = k;"),
+    "heavy_ascending": ("  qsort(e, (size_t)n_keys, sizeof(freq_entry), by_decreasing_frequency);\n  for (int32_t r = 0; r < k; ++r) {\n    keys[r] = e[r].key;",
+                        "  qsort(e, (size_t)n_keys, sizeof(freq_entry), by_decreasing_frequency);\n  for (int32_t r = 0; r < k; ++r) {\n    keys[r] = e[n_keys - 1 - r].key;"),
+    "heavy_counts_invalid": ("    if (g >= 0 && g < n_keys) e[g].cnt += 1;", "    if (g >= 0 && g < n_keys) e[g].cnt += 1;\n    else if (g == n_keys && n_keys > 0) e[0].cnt += 1;"),
 }
 
 
