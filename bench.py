@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="headline query only (for profiler runs)")
     ap.add_argument("--with-group", action="store_true", help="run the group-by workload even with --no-extras")
+    ap.add_argument("--with-ops", action="store_true", help="run the operator variants even with --no-extras")
     ap.add_argument("--skew-only", action="store_true",
                     help="skip the identity-layout query (profiler runs: one kernel name per stage)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -268,6 +269,8 @@ def main():
             del d, L
             torch.cuda.empty_cache()
         result["zipf_sweep"] = sweep_s
+    if not args.no_extras or args.with_ops:
+        result["operators"] = bench_operators(K, C, price, Cp, pp, perm, N, F, dev, stream)
     if not args.no_extras or args.with_group:
         result["group_by"] = bench_group_by(K, WU, dev, stream)
 
@@ -325,6 +328,60 @@ def bench_group_by(K, WU, dev, stream):
             "roofline_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "stages_ms": stages,
             "build_s_incl_sync": build_s,
             "layouts_agree": len({r["sum_digest"] for r in res.values()}) == 1}
+
+
+def bench_operators(K, C, price, Cp, pp, perm, N, F, dev, stream):
+    """Q1 materialization, Q2 selection and Q3a heavy hitters (Section 4.1) on the join workload, both layouts."""
+    import torch
+
+    from paper_1910_10063_amd import skew
+
+    steps = max(K // 2, 3)
+    res = {}
+    # Q1: out[j] = price[key[j]]: 4 B key read + 4 B written per row, plus the dimension column once
+    log("operators: materialize")
+    mws = skew.workspace(skew.SKEW_OP_MATERIALIZE, F, N, dev)
+    out = torch.empty_like(C)
+    ms_s = timed(lambda: skew.materialize_column(Cp, pp, ws=mws, out=out), steps, 1, stream)
+    d_s = hashlib.sha256(out[:: 997].cpu().numpy().tobytes()).hexdigest()[:16]
+    ms_i = timed(lambda: skew.materialize_column(C, price, hot_rows=0, ws=mws, out=out), steps, 1, stream)
+    d_i = hashlib.sha256(out[:: 997].cpu().numpy().tobytes()).hexdigest()[:16]
+    alg = 8.0 * F + 4.0 * N
+    res["materialize"] = {"skew_ms": ms_s, "identity_ms": ms_i, "skew_tuples_per_s": F / (ms_s * 1e-3),
+                          "identity_tuples_per_s": F / (ms_i * 1e-3), "speedup": ms_i / ms_s,
+                          "roofline_frac": alg / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, "layouts_agree": d_s == d_i}
+    # Q2: offsets of the rows with price < 100 (about 1 % of U[1, 10000])
+    log("operators: select")
+    sws = skew.workspace(skew.SKEW_OP_SELECT, F, N, dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    ms_s = timed(lambda: skew.select_fact_rows(Cp, pp, 100, ws=sws, out=(out, cnt)), steps, 1, stream)
+    n_s = int(cnt.item())
+    d_s = hashlib.sha256(out[:n_s].cpu().numpy().tobytes()).hexdigest()[:16]
+    ms_i = timed(lambda: skew.select_fact_rows(C, price, 100, hot_rows=0, ws=sws, out=(out, cnt)), steps, 1, stream)
+    n_i = int(cnt.item())
+    d_i = hashlib.sha256(out[:n_i].cpu().numpy().tobytes()).hexdigest()[:16]
+    res["select"] = {"predicate": "price < 100", "selected": n_s, "skew_ms": ms_s, "identity_ms": ms_i,
+                     "skew_tuples_per_s": F / (ms_s * 1e-3), "identity_tuples_per_s": F / (ms_i * 1e-3),
+                     "speedup": ms_i / ms_s, "layouts_agree": (n_s, d_s) == (n_i, d_i)}
+    del sws
+    # Q3a: counts of the 4000 most frequent keys on the skew layout, against the full grouped
+    # aggregate (SUM(price), COUNT(*) per key) on the identity layout, the conventional method
+    log("operators: heavy hitters")
+    hws = skew.workspace(skew.SKEW_OP_HEAVY, F, N, dev)
+    ms_h = timed(lambda: skew.heavy_hitter_counts(Cp, N, 4000, perm=perm, ws=hws), steps, 1, stream)
+    hk, hc = skew.heavy_hitter_counts(Cp, N, 4000, perm=perm, ws=hws)
+    skew.materialize_column(C, price, ws=mws, out=out)  # the value column of the full aggregate
+    gws = skew.workspace(skew.SKEW_OP_GROUP, F, N, dev)
+    gout = (torch.empty(N, dtype=torch.int64, device=dev), torch.empty(N, dtype=torch.int64, device=dev))
+    ms_f = timed(lambda: skew.group_aggregate(C, out, N, hot_groups=0, ws=gws, out=gout), max(K // 4, 2), 1, stream)
+    agree = bool((gout[1][hk.long()] == hc).all().item())
+    res["heavy_hitters"] = {"k": 4000, "skew_ms": ms_h, "skew_tuples_per_s": F / (ms_h * 1e-3),
+                            "identity_full_aggregate_ms": ms_f, "speedup_vs_full_aggregate": ms_f / ms_h,
+                            "roofline_frac": 4.0 * F / (ms_h * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            "counts_agree_with_full_aggregate": agree}
+    del gws, gout, out, hws, mws
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(C, price, cat, rows, gpu_res):

@@ -51,6 +51,9 @@ extern "C" {
 #define SKEW_OP_GROUP 3
 #define SKEW_OP_JOIN_SINGLE_PASS 4
 #define SKEW_OP_GROUP_SINGLE_PASS 5
+#define SKEW_OP_MATERIALIZE 6
+#define SKEW_OP_SELECT 7
+#define SKEW_OP_HEAVY 8
 
 /* hot_rows / hot_groups special values. */
 #define SKEW_HOT_AUTO (-1)  /* library picks the hot prefix from LDS capacity */
@@ -159,9 +162,69 @@ int group_aggregate(const int32_t *group_keys, const int32_t *values, int64_t n_
                     void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * skew_query_status - wait for `stream`, then report whether the last
- * fk_join_aggregate or group_aggregate that used this workspace saw an
- * out-of-range key (SKEW_ERANGE) or not (SKEW_OK).
+ * materialize_column - materialization (Q1 of Section 1, operator of Section
+ * 4.1): out[j] = dim_col[fact_keys[j]] for j in [0, n_fact).
+ *
+ *   fact_keys[n_fact]  int32 keys (original keys with the original column, or
+ *                      recoded keys with the permuted column).
+ *   dim_col[n_rows]    int32 dimension column.
+ *   hot_rows           rows [0, t) are copied into LDS once per workgroup and
+ *                      read there (clamped to LDS capacity); 0 = every key
+ *                      gathered from global memory; SKEW_HOT_AUTO.
+ *   out[n_fact]        int32 output; may not overlap fact_keys.
+ *   workspace          >= skew_workspace_bytes(SKEW_OP_MATERIALIZE, n_fact, n_rows).
+ *
+ * A key outside [0, n_rows) materializes 0 and sets the error flag.
+ */
+int materialize_column(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_col, int32_t n_rows,
+                       int32_t hot_rows, int32_t *out, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * select_fact_rows - selection (Q2 of Section 1, operator of Section 4.1):
+ * the offsets j of the fact rows with dim_col[fact_keys[j]] < lt, in
+ * increasing order.  The predicate is evaluated once per dimension row into a
+ * bitmap in the workspace; the bits of rows [0, hot_rows) are copied into
+ * LDS (8 rows per LDS byte, clamped to capacity).
+ *
+ *   fact_keys[n_fact]   int32 keys, n_fact < 2^31.
+ *   dim_col[n_rows]     int32 dimension column; lt: signed bound.
+ *   hot_rows            as for materialize_column, counted in rows (bits).
+ *   out_offsets[n_fact] int32 output (capacity for every row); the first
+ *                       *out_count entries are written.
+ *   out_count           int64[1] device output: number of offsets.
+ *   workspace           >= skew_workspace_bytes(SKEW_OP_SELECT, n_fact, n_rows).
+ *
+ * Keys outside [0, n_rows) never qualify and set the error flag.
+ */
+int select_fact_rows(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_col, int32_t n_rows, int32_t lt,
+                     int32_t hot_rows, int32_t *out_offsets, int64_t *out_count, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/*
+ * heavy_hitter_counts - Q3a of Section 1 on the frequency-ordered layout
+ * (Section 4.2.2): the k most frequent keys are the ranks [0, k), so only
+ * those are counted and every other row is dropped.
+ *
+ *   ranked_keys[n_fact] int32 recoded keys (ranks) in [0, n_keys).
+ *   k                   number of heavy hitters, 0 <= k <= n_keys.
+ *   perm[n_keys]        nullable: the permutation index; out_keys[r] = perm[r]
+ *                       (original key of rank r), else out_keys[r] = r.
+ *   out_keys[k]         int32 output.
+ *   out_count[k]        int64 output: rows of rank r.
+ *   workspace           >= skew_workspace_bytes(SKEW_OP_HEAVY, n_fact, n_keys).
+ *
+ * With a layout built on the same column, (out_keys, out_count) are the k most
+ * frequent keys with their counts, most frequent first, equal counts by
+ * ascending key.  Keys outside [0, n_keys) are dropped and set the error flag.
+ */
+int heavy_hitter_counts(const int32_t *ranked_keys, int64_t n_fact, int32_t n_keys, int32_t k, const int32_t *perm,
+                        int32_t *out_keys, int64_t *out_count, void *workspace, size_t workspace_bytes,
+                        void *stream);
+
+/*
+ * skew_query_status - wait for `stream`, then report whether the last query
+ * call that used this workspace saw an out-of-range key (SKEW_ERANGE) or not
+ * (SKEW_OK).
  */
 int skew_query_status(const void *workspace, size_t workspace_bytes, void *stream);
 
@@ -179,6 +242,9 @@ int skew_profile_report(char *names, int names_bytes, float *ms, int *calls, int
  * current device, or a negative code. */
 int32_t skew_max_hot_rows(int32_t group_by_category);
 int32_t skew_max_hot_groups(void);
+/* op: SKEW_OP_MATERIALIZE (rows), SKEW_OP_SELECT (rows, i.e. bits), SKEW_OP_HEAVY
+ * (ranks counted in LDS; ranks in [capacity, k) use global atomics). */
+int64_t skew_max_hot(int op);
 
 #ifdef __cplusplus
 }

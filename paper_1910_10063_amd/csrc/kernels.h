@@ -74,6 +74,19 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
                        uint32_t *words, int32_t *flag, void *part_ws, size_t part_bytes, const DeviceInfo &dev,
                        hipStream_t s);
 
+// ---- operator variants (Section 4.1) ----
+int32_t materialize_max_hot_rows(const DeviceInfo &dev);
+int64_t select_max_hot_rows(const DeviceInfo &dev);
+int32_t heavy_max_lds_ranks(const DeviceInfo &dev);
+size_t select_workspace_bytes(int64_t n_fact, int32_t n_rows, int32_t blocks);
+hipError_t launch_materialize(const int32_t *keys, int64_t n, const int32_t *col, int32_t n_rows, int32_t t,
+                              int32_t *out, int32_t *flag, const DeviceInfo &dev, hipStream_t s);
+hipError_t launch_select(const int32_t *keys, int64_t n_fact, const int32_t *col, int32_t n_rows, int32_t lt,
+                         int32_t t, int32_t *out, int64_t *count, int32_t *flag, void *ws, const DeviceInfo &dev,
+                         hipStream_t s);
+hipError_t launch_heavy(const int32_t *keys, int64_t n_fact, int32_t n_keys, int32_t k, const int32_t *perm,
+                        int32_t *out_keys, int64_t *out_count, int32_t *flag, const DeviceInfo &dev, hipStream_t s);
+
 enum GroupMode { kGroupRange = 0, kGroupHash = 1, kGroupAtomic = 2 };
 hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact, int32_t n_groups, GroupMode mode,
                         int32_t hot_groups, const int32_t *perm, int64_t *out_sum, int64_t *out_cnt,

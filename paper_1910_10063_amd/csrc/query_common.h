@@ -229,4 +229,35 @@ __device__ __forceinline__ int32_t slice_of_item(const uint32_t *soff, int32_t P
   return a;
 }
 
+// Copy words [base, base + len) of a 4-byte column into LDS (16-byte loads
+// when the source is 16-byte aligned at base).
+__device__ __forceinline__ void stage_words(uint32_t *dst, const uint32_t *words, int64_t base, int32_t len) {
+  const uint32_t *src = words + base;
+  if (((uintptr_t)src & 15u) == 0) {
+    const int nv = len >> 2;
+    for (int i = threadIdx.x; i < nv; i += blockDim.x)
+      reinterpret_cast<uint4 *>(dst)[i] = reinterpret_cast<const uint4 *>(src)[i];
+    for (int i = 4 * nv + threadIdx.x; i < len; i += blockDim.x) dst[i] = src[i];
+  } else {
+    for (int i = threadIdx.x; i < len; i += blockDim.x) dst[i] = src[i];
+  }
+}
+
+// Hot prefix + cold lookup state of the single-pass kernel.
+struct HotCtx {
+  const uint32_t *hot;  // LDS
+  rsrc_t words;
+  uint32_t t, tclamp;
+};
+
+__device__ __forceinline__ uint32_t fetch_hot_or_global(const HotCtx &h, uint32_t uk) {
+  // Two reads without branching: a clamped LDS read and a buffer gather whose
+  // index is pushed out of range for hot keys (it returns 0 and issues no
+  // memory traffic); the select keeps the right one.
+  const bool hot = uk < h.t;
+  const uint32_t wl = h.hot[uk < h.tclamp ? uk : h.tclamp];
+  const uint32_t wg = buffer_load_record(h.words, (int32_t)(hot ? 0xFFFFFFFFu : uk), 0, 0, 0);
+  return hot ? wl : wg;
+}
+
 }  // namespace skew

@@ -202,6 +202,11 @@ size_t skew_workspace_bytes(int op, int64_t n_fact, int32_t n_keys) {
       return join_ws(n_keys);
     case SKEW_OP_GROUP_SINGLE_PASS:
       return group_ws(n_keys);
+    case SKEW_OP_MATERIALIZE:
+    case SKEW_OP_HEAVY:
+      return skew::kFlagBytes;
+    case SKEW_OP_SELECT:
+      return skew::kFlagBytes + round_up(skew::select_workspace_bytes(n_fact, n_keys, kPartBlocks));
     default:
       return 0;
   }
@@ -346,6 +351,85 @@ int group_aggregate(const int32_t *group_keys, const int32_t *values, int64_t n_
   return ok();
 }
 
+int materialize_column(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_col, int32_t n_rows,
+                       int32_t hot_rows, int32_t *out, void *workspace, size_t workspace_bytes, void *stream) {
+  if (n_fact < 0) return fail(SKEW_EINVAL, "n_fact must be >= 0");
+  if (n_rows < 1) return fail(SKEW_EINVAL, "n_rows must be >= 1");
+  if (n_fact > 0 && (!fact_keys || !out)) return fail(SKEW_EINVAL, "fact_keys and out are required");
+  if (!dim_col) return fail(SKEW_EINVAL, "dim_col is NULL");
+  if (!workspace) return fail(SKEW_EINVAL, "workspace is NULL");
+  if (hot_rows < SKEW_HOT_AUTO) return fail(SKEW_EINVAL, "hot_rows must be >= 0 or SKEW_HOT_AUTO");
+  if (!aligned4(fact_keys) || !aligned4(dim_col) || !aligned4(out))
+    return fail(SKEW_EINVAL, "32-bit arrays must be 4-byte aligned");
+  if (n_fact > 0 && out + n_fact > fact_keys && fact_keys + n_fact > out)
+    return fail(SKEW_EINVAL, "out overlaps fact_keys");
+  if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
+  if (workspace_bytes < skew::kFlagBytes)
+    return fail(SKEW_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, skew::kFlagBytes);
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const int32_t t = hot_rows == SKEW_HOT_AUTO ? skew::materialize_max_hot_rows(dev) : hot_rows;
+  const hipStream_t s = (hipStream_t)stream;
+  const hipError_t e = skew::launch_materialize(fact_keys, n_fact, dim_col, n_rows, t, out, (int32_t *)workspace, dev, s);
+  if (e != hipSuccess) return hip_fail(e, "materialize launch");
+  if (check_enabled()) return read_flag(workspace, s);
+  return ok();
+}
+
+int select_fact_rows(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_col, int32_t n_rows, int32_t lt,
+                     int32_t hot_rows, int32_t *out_offsets, int64_t *out_count, void *workspace,
+                     size_t workspace_bytes, void *stream) {
+  if (n_fact < 0 || n_fact >= ((int64_t)1 << 31)) return fail(SKEW_EINVAL, "n_fact must be in [0, 2^31)");
+  if (n_rows < 1) return fail(SKEW_EINVAL, "n_rows must be >= 1");
+  if (n_fact > 0 && (!fact_keys || !out_offsets)) return fail(SKEW_EINVAL, "fact_keys and out_offsets are required");
+  if (!dim_col || !out_count) return fail(SKEW_EINVAL, "dim_col and out_count are required");
+  if (!workspace) return fail(SKEW_EINVAL, "workspace is NULL");
+  if (hot_rows < SKEW_HOT_AUTO) return fail(SKEW_EINVAL, "hot_rows must be >= 0 or SKEW_HOT_AUTO");
+  if (!aligned4(fact_keys) || !aligned4(dim_col) || !aligned4(out_offsets))
+    return fail(SKEW_EINVAL, "32-bit arrays must be 4-byte aligned");
+  if ((uintptr_t)out_count & 7u) return fail(SKEW_EINVAL, "out_count must be 8-byte aligned");
+  if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = skew_workspace_bytes(SKEW_OP_SELECT, n_fact, n_rows);
+  if (workspace_bytes < need) return fail(SKEW_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const skew::DeviceInfo pdev = part_device(dev);
+  int64_t t = hot_rows == SKEW_HOT_AUTO ? skew::select_max_hot_rows(dev) : hot_rows;
+  if (t > n_rows) t = n_rows;
+  const hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  const hipError_t e = skew::launch_select(fact_keys, n_fact, dim_col, n_rows, lt, (int32_t)t, out_offsets, out_count,
+                                           (int32_t *)ws, ws + skew::kFlagBytes, pdev, s);
+  if (e != hipSuccess) return hip_fail(e, "select launch");
+  if (check_enabled()) return read_flag(workspace, s);
+  return ok();
+}
+
+int heavy_hitter_counts(const int32_t *ranked_keys, int64_t n_fact, int32_t n_keys, int32_t k, const int32_t *perm,
+                        int32_t *out_keys, int64_t *out_count, void *workspace, size_t workspace_bytes,
+                        void *stream) {
+  if (n_fact < 0) return fail(SKEW_EINVAL, "n_fact must be >= 0");
+  if (n_keys < 1) return fail(SKEW_EINVAL, "n_keys must be >= 1");
+  if (k < 0 || k > n_keys) return fail(SKEW_EINVAL, "k must be in [0, n_keys]");
+  if (n_fact > 0 && !ranked_keys) return fail(SKEW_EINVAL, "ranked_keys is NULL");
+  if (k > 0 && (!out_keys || !out_count)) return fail(SKEW_EINVAL, "outputs are required");
+  if (!workspace) return fail(SKEW_EINVAL, "workspace is NULL");
+  if (!aligned4(ranked_keys) || !aligned4(perm) || !aligned4(out_keys))
+    return fail(SKEW_EINVAL, "32-bit arrays must be 4-byte aligned");
+  if ((uintptr_t)out_count & 7u) return fail(SKEW_EINVAL, "out_count must be 8-byte aligned");
+  if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
+  if (workspace_bytes < skew::kFlagBytes)
+    return fail(SKEW_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, skew::kFlagBytes);
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const hipStream_t s = (hipStream_t)stream;
+  const hipError_t e =
+      skew::launch_heavy(ranked_keys, n_fact, n_keys, k, perm, out_keys, out_count, (int32_t *)workspace, dev, s);
+  if (e != hipSuccess) return hip_fail(e, "heavy hitter launch");
+  if (check_enabled()) return read_flag(workspace, s);
+  return ok();
+}
+
 int skew_query_status(const void *workspace, size_t workspace_bytes, void *stream) {
   if (!workspace || workspace_bytes < skew::kFlagBytes) return fail(SKEW_EINVAL, "workspace is NULL or too small");
   return read_flag(workspace, (hipStream_t)stream);
@@ -405,6 +489,21 @@ int32_t skew_max_hot_groups(void) {
   skew::DeviceInfo dev;
   if (int rc = device_info(&dev)) return rc;
   return skew::group_max_hot_groups(dev);
+}
+
+int64_t skew_max_hot(int op) {
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  switch (op) {
+    case SKEW_OP_MATERIALIZE:
+      return skew::materialize_max_hot_rows(dev);
+    case SKEW_OP_SELECT:
+      return skew::select_max_hot_rows(dev);
+    case SKEW_OP_HEAVY:
+      return skew::heavy_max_lds_ranks(dev);
+    default:
+      return fail(SKEW_EINVAL, "op %d has no hot prefix of its own", op);
+  }
 }
 
 }  // extern "C"

@@ -28,13 +28,16 @@ SKEW_OP_JOIN = 2
 SKEW_OP_GROUP = 3
 SKEW_OP_JOIN_SINGLE_PASS = 4
 SKEW_OP_GROUP_SINGLE_PASS = 5
+SKEW_OP_MATERIALIZE = 6
+SKEW_OP_SELECT = 7
+SKEW_OP_HEAVY = 8
 
 SKEW_HOT_AUTO = -1
 SKEW_HOT_NONE = -2
 
 EXPORTED = ("skew_last_error", "skew_workspace_bytes", "build_skew_layout", "fk_join_aggregate", "group_aggregate",
             "skew_query_status", "skew_profile_enable", "skew_profile_report", "skew_max_hot_rows",
-            "skew_max_hot_groups")
+            "skew_max_hot_groups", "materialize_column", "select_fact_rows", "heavy_hitter_counts", "skew_max_hot")
 
 
 class SkewError(RuntimeError):
@@ -75,6 +78,14 @@ def load_library(path: str = LIB_PATH):
     lib.skew_profile_enable.restype = None
     lib.skew_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_int, P, P, ctypes.c_int]
     lib.skew_profile_report.restype = ctypes.c_int
+    lib.materialize_column.argtypes = [P, I64, P, I32, I32, P, P, SZ, P]
+    lib.materialize_column.restype = ctypes.c_int
+    lib.select_fact_rows.argtypes = [P, I64, P, I32, I32, I32, P, P, P, SZ, P]
+    lib.select_fact_rows.restype = ctypes.c_int
+    lib.heavy_hitter_counts.argtypes = [P, I64, I32, I32, P, P, P, P, SZ, P]
+    lib.heavy_hitter_counts.restype = ctypes.c_int
+    lib.skew_max_hot.argtypes = [ctypes.c_int]
+    lib.skew_max_hot.restype = I64
     if path == LIB_PATH:
         _lib = lib
     return lib
@@ -200,6 +211,67 @@ def group_aggregate(group_keys: torch.Tensor, values: torch.Tensor, n_groups: in
     _check(lib.group_aggregate(_ptr(group_keys), _ptr(values), group_keys.numel(), n_groups, int(hot_groups),
                                _ptr(perm), _ptr(out[0]), _ptr(out[1]), _ptr(ws), ws.numel(), _stream(dev)))
     return out
+
+
+def materialize_column(fact_keys: torch.Tensor, col: torch.Tensor, hot_rows: int = SKEW_HOT_AUTO,
+                       ws: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """out[j] = col[fact_keys[j]] (0 for out-of-range keys), int32."""
+    lib = load_library()
+    _need(fact_keys, torch.int32, "fact_keys")
+    _need(col, torch.int32, "col")
+    dev = fact_keys.device
+    if out is None:
+        out = torch.empty_like(fact_keys)
+    _need(out, torch.int32, "out")
+    if out.numel() != fact_keys.numel():
+        raise ValueError("out must have one entry per fact key")
+    if ws is None:
+        ws = workspace(SKEW_OP_MATERIALIZE, fact_keys.numel(), col.numel(), dev)
+    _check(lib.materialize_column(_ptr(fact_keys), fact_keys.numel(), _ptr(col), col.numel(), int(hot_rows),
+                                  _ptr(out), _ptr(ws), ws.numel(), _stream(dev)))
+    return out
+
+
+def select_fact_rows(fact_keys: torch.Tensor, col: torch.Tensor, lt: int, hot_rows: int = SKEW_HOT_AUTO,
+                     ws: torch.Tensor | None = None,
+                     out: tuple[torch.Tensor, torch.Tensor] | None = None) -> tuple[torch.Tensor, torch.Tensor]:
+    """(offsets int32[n_fact] of which the first count are valid, count int64[1]) for col[key] < lt."""
+    lib = load_library()
+    _need(fact_keys, torch.int32, "fact_keys")
+    _need(col, torch.int32, "col")
+    dev = fact_keys.device
+    if out is None:
+        out = (torch.empty(max(fact_keys.numel(), 1), dtype=torch.int32, device=dev),
+               torch.empty(1, dtype=torch.int64, device=dev))
+    if ws is None:
+        ws = workspace(SKEW_OP_SELECT, fact_keys.numel(), col.numel(), dev)
+    _check(lib.select_fact_rows(_ptr(fact_keys), fact_keys.numel(), _ptr(col), col.numel(), int(lt), int(hot_rows),
+                                _ptr(out[0]), _ptr(out[1]), _ptr(ws), ws.numel(), _stream(dev)))
+    return out
+
+
+def heavy_hitter_counts(ranked_keys: torch.Tensor, n_keys: int, k: int, perm: torch.Tensor | None = None,
+                        ws: torch.Tensor | None = None) -> tuple[torch.Tensor, torch.Tensor]:
+    """(keys int32[k], counts int64[k]) of ranks [0, k) on the frequency-ordered layout."""
+    lib = load_library()
+    _need(ranked_keys, torch.int32, "ranked_keys")
+    if perm is not None:
+        _need(perm, torch.int32, "perm")
+    dev = ranked_keys.device
+    keys = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
+    counts = torch.empty(max(k, 1), dtype=torch.int64, device=dev)
+    if ws is None:
+        ws = workspace(SKEW_OP_HEAVY, ranked_keys.numel(), n_keys, dev)
+    _check(lib.heavy_hitter_counts(_ptr(ranked_keys), ranked_keys.numel(), n_keys, int(k), _ptr(perm), _ptr(keys),
+                                   _ptr(counts), _ptr(ws), ws.numel(), _stream(dev)))
+    return keys[:k], counts[:k]
+
+
+def max_hot(op: int) -> int:
+    v = load_library().skew_max_hot(op)
+    if v < 0:
+        _check(int(v))
+    return int(v)
 
 
 def query_status(ws: torch.Tensor) -> int:

@@ -134,3 +134,75 @@ def test_valid_call_without_gpu_reports_edevice(lib):
         pytest.skip("a GPU is present")
     assert _join(lib) == skew.SKEW_EDEVICE
     assert "device" in lib.skew_last_error().decode()
+
+
+def _mat(lib, **kw):
+    a = dict(keys=A, n=10, col=A2, n_rows=5, hot=0, out=ctypes.c_void_p(0x80000), ws=WS, wsb=1 << 20)
+    a.update(kw)
+    return lib.materialize_column(a["keys"], a["n"], a["col"], a["n_rows"], a["hot"], a["out"], a["ws"], a["wsb"], S)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=-1), skew.SKEW_EINVAL),
+    (dict(n_rows=0), skew.SKEW_EINVAL),
+    (dict(keys=NULL), skew.SKEW_EINVAL),
+    (dict(col=NULL), skew.SKEW_EINVAL),
+    (dict(out=NULL), skew.SKEW_EINVAL),
+    (dict(out=ctypes.c_void_p(0x10008)), skew.SKEW_EINVAL),  # overlaps the keys
+    (dict(hot=-3), skew.SKEW_EINVAL),
+    (dict(col=MIS), skew.SKEW_EINVAL),
+    (dict(wsb=100), skew.SKEW_ENOSPACE),
+])
+def test_materialize_rejects(lib, kw, code):
+    assert _mat(lib, **kw) == code
+
+
+def _sel(lib, **kw):
+    a = dict(keys=A, n=10, col=A2, n_rows=5, lt=7, hot=0, out=ctypes.c_void_p(0x80000), cnt=ctypes.c_void_p(0x90000),
+             ws=WS, wsb=1 << 26)
+    a.update(kw)
+    return lib.select_fact_rows(a["keys"], a["n"], a["col"], a["n_rows"], a["lt"], a["hot"], a["out"], a["cnt"],
+                                a["ws"], a["wsb"], S)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=-1), skew.SKEW_EINVAL),
+    (dict(n=1 << 31), skew.SKEW_EINVAL),
+    (dict(n_rows=0), skew.SKEW_EINVAL),
+    (dict(keys=NULL), skew.SKEW_EINVAL),
+    (dict(cnt=NULL), skew.SKEW_EINVAL),
+    (dict(cnt=ctypes.c_void_p(0x90004)), skew.SKEW_EINVAL),
+    (dict(hot=-5), skew.SKEW_EINVAL),
+    (dict(wsb=1000), skew.SKEW_ENOSPACE),
+])
+def test_select_rejects(lib, kw, code):
+    assert _sel(lib, **kw) == code
+
+
+def _heavy(lib, **kw):
+    a = dict(keys=A, n=10, n_keys=5, k=3, perm=NULL, ok=A2, oc=ctypes.c_void_p(0x80000), ws=WS, wsb=1 << 20)
+    a.update(kw)
+    return lib.heavy_hitter_counts(a["keys"], a["n"], a["n_keys"], a["k"], a["perm"], a["ok"], a["oc"], a["ws"],
+                                   a["wsb"], S)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=-1), skew.SKEW_EINVAL),
+    (dict(n_keys=0), skew.SKEW_EINVAL),
+    (dict(k=-1), skew.SKEW_EINVAL),
+    (dict(k=6), skew.SKEW_EINVAL),
+    (dict(keys=NULL), skew.SKEW_EINVAL),
+    (dict(ok=NULL), skew.SKEW_EINVAL),
+    (dict(oc=ctypes.c_void_p(0x80004)), skew.SKEW_EINVAL),
+    (dict(wsb=10), skew.SKEW_ENOSPACE),
+])
+def test_heavy_rejects(lib, kw, code):
+    assert _heavy(lib, **kw) == code
+
+
+def test_operator_workspace_sizes(lib):
+    assert lib.skew_workspace_bytes(skew.SKEW_OP_MATERIALIZE, 10, 10) == 256
+    assert lib.skew_workspace_bytes(skew.SKEW_OP_HEAVY, 10, 10) == 256
+    # bitmap + one round of segments (with the chunk slack) + tables
+    assert lib.skew_workspace_bytes(skew.SKEW_OP_SELECT, 1 << 20, 1000) >= 256 + 4 * (1 << 20)
+    assert lib.skew_workspace_bytes(skew.SKEW_OP_SELECT, 3_000_000_000, 10) < 4 * 3_000_000_000

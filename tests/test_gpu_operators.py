@@ -1,0 +1,214 @@
+"""GPU parity of the operator variants (Section 4.1) against the CPU oracle, bit-exact.
+
+Materialization (Q1), selection into increasing fact offsets (Q2) and the
+heavy-hitter counts of Q3a on the frequency-ordered layout, for every hot
+prefix size, both layouts, ragged and unaligned columns, several rounds of the
+selection, out-of-range keys, and the workload sizes of the join.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1910_10063_amd import skew
+from paper_1910_10063_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def small():
+    k, N, F, s = 1, 100_000, 1_000_000, 1.0
+    say(f"operators: small workload N={N} F={F} s={s}")
+    h = W.host_join_inputs(k, N, F, s)
+    ref = oracle.build_layout(h["fact"], N, h["price"], h["category"])
+    d = {n: to_dev(h[n]) for n in ("fact", "price")}
+    L = skew.build_skew_layout(d["fact"], N, d["price"])
+    return dict(N=N, F=F, h=h, ref=ref, d=d, L=L)
+
+
+# ---------------------------------------------------------------- Q1
+@pytest.mark.parametrize("t", [0, 1, 3, 64, 4096, 39_000, 100_000, 100_003, skew.SKEW_HOT_AUTO])
+@pytest.mark.parametrize("layout", ["skew", "identity"])
+def test_materialize_every_t(small, t, layout):
+    say(f"materialize t={t} {layout}")
+    h, ref, d, L = small["h"], small["ref"], small["d"], small["L"]
+    keys, col = (L.fact_recoded, L.price) if layout == "skew" else (d["fact"], d["price"])
+    out = skew.materialize_column(keys, col, hot_rows=t)
+    want, inv = oracle.materialize(h["fact"], h["price"])
+    assert inv == 0
+    assert (host(out) == want).all()
+
+
+@pytest.mark.parametrize("koff,ooff", [(0, 0), (1, 1), (3, 3), (0, 1), (2, 0), (1, 3)])
+@pytest.mark.parametrize("F", [0, 1, 3, 5, 4097, 65541, 4 * 1024 * 4 * 3 + 7])
+def test_materialize_ragged_unaligned(koff, ooff, F):
+    say(f"materialize ragged F={F} key offset {koff} out offset {ooff}")
+    rng = np.random.default_rng(F * 7 + koff)
+    N = 5000
+    col = rng.integers(-2**31, 2**31, N, dtype=np.int64).astype(np.int32)
+    keys = rng.integers(0, N, F + 8).astype(np.int32)
+    kd = to_dev(keys)[koff:koff + F]
+    ob = torch.full((F + 8,), 7, dtype=torch.int32, device=DEV)
+    out = ob[ooff:ooff + F]
+    skew.materialize_column(kd, to_dev(col), hot_rows=1000, out=out)
+    want, _ = oracle.materialize(keys[koff:koff + F], col)
+    got = host(ob)
+    assert (got[ooff:ooff + F] == want).all()
+    assert (got[:ooff] == 7).all() and (got[ooff + F:] == 7).all(), "wrote outside out"
+
+
+def test_materialize_out_of_range_keys():
+    say("materialize out-of-range keys")
+    N = 1000
+    col = np.arange(N, dtype=np.int32) * 3 + 1
+    keys = np.array([0, 5, -1, N, N + 7, 2**31 - 1, 999, -2**31] * 1000, dtype=np.int32)
+    ws = skew.workspace(skew.SKEW_OP_MATERIALIZE, keys.size, N, DEV)
+    out = skew.materialize_column(to_dev(keys), to_dev(col), hot_rows=100, ws=ws)
+    want, inv = oracle.materialize(keys, col)
+    assert inv > 0 and (host(out) == want).all()
+    with pytest.raises(skew.SkewError):
+        skew.query_status(ws)
+    skew.materialize_column(to_dev(keys[:2]), to_dev(col), ws=ws)
+    assert skew.query_status(ws) == skew.SKEW_OK
+
+
+@pytest.mark.slow
+def test_materialize_full_size_sampled():
+    """1e7-row dimension, 2^28 + 5 Zipf(1.0) keys (one full round of the join), sampled rows."""
+    N, F = 10_000_000, (1 << 28) + 5
+    say(f"materialize full size N={N} F={F}")
+    d = W.device_join_inputs(2, N, F, 1.0, DEV)
+    L = skew.build_skew_layout(d["fact"], N, d["price"])
+    out = skew.materialize_column(L.fact_recoded, L.price)
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([np.arange(0, 64), rng.integers(0, F, 200_000), np.arange(F - 64, F)])
+    it = torch.from_numpy(idx).to(DEV)
+    keys = host(d["fact"][it])
+    want, _ = oracle.materialize(keys, host(d["price"]))
+    assert (host(out[it]) == want).all()
+    del d, L, out
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- Q2
+def select_host(keys_d, col_d, lt, t, ws=None):
+    off, cnt = skew.select_fact_rows(keys_d, col_d, lt, hot_rows=t, ws=ws)
+    n = int(host(cnt)[0])
+    return host(off)[:n].astype(np.int64)
+
+
+@pytest.mark.parametrize("t", [0, 1, 31, 32, 33, 4096, 99_999, 100_000, skew.SKEW_HOT_AUTO])
+@pytest.mark.parametrize("lt", [-5, 1, 2, 100, 5000, 10_001])
+def test_select_every_t(small, t, lt):
+    say(f"select t={t} lt={lt}")
+    h, d, L = small["h"], small["d"], small["L"]
+    want = oracle.select(h["fact"], h["price"], lt)
+    assert (select_host(L.fact_recoded, L.price, lt, t) == want).all()
+    if t in (0, skew.SKEW_HOT_AUTO):
+        assert (select_host(d["fact"], d["price"], lt, t) == want).all()
+
+
+@pytest.mark.parametrize("offset", [0, 1, 2, 3])
+@pytest.mark.parametrize("F", [0, 1, 2, 3, 4, 5, 63, 64, 65, 4097, 262_147])
+def test_select_ragged_unaligned(offset, F):
+    say(f"select ragged F={F} offset {offset}")
+    rng = np.random.default_rng(F + 11 * offset)
+    N = 3000
+    col = rng.integers(0, 100, N).astype(np.int32)
+    keys = rng.integers(0, N, F + 4).astype(np.int32)
+    kd = to_dev(keys)[offset:offset + F]
+    got = select_host(kd, to_dev(col), 37, 500)
+    want = oracle.select(keys[offset:offset + F], col, 37)
+    assert got.size == want.size and (got == want).all()
+
+
+def test_select_out_of_range_keys():
+    say("select out-of-range keys")
+    N = 700
+    col = np.zeros(N, dtype=np.int32)
+    keys = np.array([1, -1, N, 3, N + 31, 2**31 - 1, 699, -2**31, 0] * 999, dtype=np.int32)
+    ws = skew.workspace(skew.SKEW_OP_SELECT, keys.size, N, DEV)
+    got = select_host(to_dev(keys), to_dev(col), 1, 64, ws=ws)
+    assert (got == oracle.select(keys, col, 1)).all()
+    with pytest.raises(skew.SkewError):
+        skew.query_status(ws)
+
+
+@pytest.mark.slow
+def test_select_two_rounds():
+    """2^28 + 2^20 + 3 rows: two rounds of the segment compaction, counts and every offset exact."""
+    N, F = 1_000_000, (1 << 28) + (1 << 20) + 3
+    say(f"select two rounds N={N} F={F}")
+    d = W.device_join_inputs(3, N, F, 1.0, DEV)
+    L = skew.build_skew_layout(d["fact"], N, d["price"])
+    lt = 1000  # ~10% of U[1, 10000]
+    off, cnt = skew.select_fact_rows(L.fact_recoded, L.price, lt)
+    n = int(host(cnt)[0])
+    got = host(off[:n])
+    del off
+    keys = host(d["fact"])
+    want = oracle.select(keys, host(d["price"]), lt)
+    assert n == want.size
+    assert (got.astype(np.int64) == want).all()
+    del d, L
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- Q3a
+@pytest.mark.parametrize("k", [0, 1, 15, 16, 17, 100, 4000, 39_000, 60_000, 100_000])
+def test_heavy_hitters(small, k):
+    say(f"heavy hitters k={k}")
+    N, h, L = small["N"], small["h"], small["L"]
+    keys, counts = skew.heavy_hitter_counts(L.fact_recoded, N, k, perm=L.perm)
+    wk, wc = oracle.heavy_hitters(h["fact"], N, k)
+    assert (host(keys) == wk).all() and (host(counts) == wc).all()
+    r, c2 = skew.heavy_hitter_counts(L.fact_recoded, N, k)
+    assert (host(r) == np.arange(k)).all() and (host(c2) == wc).all()
+
+
+@pytest.mark.parametrize("offset", [0, 1, 3])
+@pytest.mark.parametrize("F", [0, 1, 7, 4099, 1_000_003])
+def test_heavy_hitters_ragged(offset, F):
+    say(f"heavy hitters ragged F={F} offset {offset}")
+    rng = np.random.default_rng(F + offset)
+    n = 2000
+    G = (rng.zipf(1.2, F + 4) % n).astype(np.int32)
+    ref = oracle.build_layout(G[offset:offset + F], n)
+    Gd = to_dev(ref.fact_recoded)
+    keys, counts = skew.heavy_hitter_counts(Gd, n, 300, perm=to_dev(ref.perm))
+    wk, wc = oracle.heavy_hitters(G[offset:offset + F], n, 300)
+    assert (host(keys) == wk).all() and (host(counts) == wc).all()
+    # an unaligned view of the same ranks
+    buf = to_dev(np.concatenate([np.zeros(offset, np.int32), ref.fact_recoded]))
+    _, c3 = skew.heavy_hitter_counts(buf[offset:], n, 300)
+    assert (host(c3) == wc).all()
+
+
+def test_heavy_hitters_out_of_range():
+    say("heavy hitters out-of-range ranks")
+    n = 100
+    G = np.array([0, 1, 1, -1, n, 5, 2**31 - 1] * 500, dtype=np.int32)
+    ws = skew.workspace(skew.SKEW_OP_HEAVY, G.size, n, DEV)
+    _, c = skew.heavy_hitter_counts(to_dev(G), n, 10, ws=ws)
+    assert host(c).tolist() == [500, 1000, 0, 0, 0, 500, 0, 0, 0, 0]
+    with pytest.raises(skew.SkewError):
+        skew.query_status(ws)
