@@ -22,7 +22,7 @@ _lib = None
 def compile_source(src: str, out: str) -> str:
     """Compile an oracle source file with gcc into a shared library (plain -O2)."""
     tmp = out + f".tmp{os.getpid()}"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, src])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
     os.replace(tmp, out)
     return out
 
@@ -61,6 +61,8 @@ def bind(path: str):
     lib.oracle_select.restype = I64
     lib.oracle_heavy_hitters.argtypes = [P, I64, I32, I32, P, P]
     lib.oracle_heavy_hitters.restype = I32
+    lib.oracle_cache_model.argtypes = [P, I64, I64]
+    lib.oracle_cache_model.restype = ctypes.c_double
     return lib
 
 
@@ -173,6 +175,23 @@ def heavy_hitters(G, n_keys: int, k: int):
     counts = np.empty(max(min(k, n_keys), 1), dtype=np.int64)
     kk = _load().oracle_heavy_hitters(_p(G), G.size, n_keys, int(k), _p(keys), _p(counts))
     return keys[:kk].copy(), counts[:kk].copy()
+
+
+def cache_model(f, cache_lines: int) -> float:
+    """Hit rate of the stack-distance model of Section 3.4 for line frequencies f (summing to 1)."""
+    f = _c(f, np.float64)
+    return float(_load().oracle_cache_model(_p(f), f.size, int(cache_lines)))
+
+
+def line_frequencies(counts_by_key, values_per_line: int):
+    """Access frequency of every cache line of `values_per_line` consecutive keys (Section 3.4)."""
+    c = np.asarray(counts_by_key, dtype=np.float64)
+    n_lines = (c.size + values_per_line - 1) // values_per_line
+    pad = np.zeros(n_lines * values_per_line)
+    pad[:c.size] = c
+    lines = pad.reshape(n_lines, values_per_line).sum(axis=1)
+    tot = lines.sum()
+    return lines / tot if tot > 0 else lines
 
 
 class Layout:

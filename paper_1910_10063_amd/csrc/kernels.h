@@ -24,7 +24,7 @@ hipError_t launch_histogram(const int32_t *keys, int64_t n, int32_t n_keys, uint
 // of n_keys u32 plus 256 * sort_tiles(n_keys) u32 of digit histograms.
 hipError_t launch_rank_sort(const uint32_t *counts_by_key, int32_t n_keys, int64_t n_fact, int32_t *perm,
                             uint32_t *counts_by_rank, uint32_t *keys_a, uint32_t *keys_b, int32_t *vals_a,
-                            int32_t *vals_b, uint32_t *digit_hist, hipStream_t s);
+                            int32_t *vals_b, uint32_t *digit_hist, uint32_t *scan_scratch, hipStream_t s);
 hipError_t launch_inverse(const int32_t *perm, int32_t n, int32_t *rank, hipStream_t s);
 hipError_t launch_permute_dims(const int32_t *perm, int32_t n, const int32_t *price, const int8_t *cat,
                                int32_t *price_out, int8_t *cat_out, hipStream_t s);
@@ -33,7 +33,10 @@ hipError_t launch_recode(const int32_t *keys, int64_t n, const int32_t *rank, in
 
 // ---- prefix sums and cold-item partitioning ----
 struct SliceTables;
-hipError_t launch_exclusive_scan(uint32_t *a, int64_t n, uint32_t *total, hipStream_t s);
+// Exclusive prefix sum in place; `total` (nullable) receives the sum.  scratch
+// (nullable, kScanBlocks words) lets large arrays use many workgroups.
+constexpr int kScanBlocks = 512;
+hipError_t launch_exclusive_scan(uint32_t *a, int64_t n, uint32_t *total, uint32_t *scratch, hipStream_t s);
 // Scan of the (slice, block) counts and the slice table.
 hipError_t launch_partition_plan(const SliceTables &tab, int32_t P, int32_t B, hipStream_t s);
 // Move every block's cold items into slice order, as 2-byte offsets inside
@@ -41,6 +44,17 @@ hipError_t launch_partition_plan(const SliceTables &tab, int32_t P, int32_t B, h
 hipError_t launch_partition_scatter(const SliceTables &tab, int32_t P, int32_t B, const int32_t *seg_keys,
                                     const int32_t *seg_vals, int64_t seg_cap, int32_t t, int32_t wshift,
                                     uint16_t *out_local, int32_t *out_vals, hipStream_t s);
+
+// Partitioned key histogram (large fact columns, at most kMaxSlices slices of
+// 32768 keys).  counts must be zeroed; keys outside [0, n_keys) set *flag.
+struct HistPlan {
+  int32_t blocks, slices;
+  int64_t round, seg_cap;
+};
+HistPlan hist_plan(int64_t n_fact, int32_t n_keys, const DeviceInfo &dev);
+size_t hist_partition_bytes(const HistPlan &pl);
+hipError_t launch_histogram_partitioned(const int32_t *keys, int64_t n_fact, int32_t n_keys, uint32_t *counts,
+                                        int32_t *flag, void *part_ws, const HistPlan &pl, hipStream_t s);
 
 // ---- queries (Section 4) ----
 constexpr int kJoinThreads = 1024;

@@ -295,7 +295,7 @@ hipError_t launch_histogram(const int32_t *keys, int64_t n, int32_t n_keys, uint
 
 hipError_t launch_rank_sort(const uint32_t *counts_by_key, int32_t n_keys, int64_t n_fact, int32_t *perm,
                             uint32_t *counts_by_rank, uint32_t *keys_a, uint32_t *keys_b, int32_t *vals_a,
-                            int32_t *vals_b, uint32_t *digit_hist, hipStream_t s) {
+                            int32_t *vals_b, uint32_t *digit_hist, uint32_t *scan_scratch, hipStream_t s) {
   // Counts lie in [0, n_fact]; sort keys maxv - count need `bits` bits.
   int bits = 1;
   while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)n_fact) ++bits;
@@ -316,7 +316,7 @@ hipError_t launch_rank_sort(const uint32_t *counts_by_key, int32_t n_keys, int64
     else
       hipLaunchKernelGGL(radix_upsweep_kernel<false>, dim3(tiles), dim3(kSortThreads), 0, s, kin, n_keys, shift, maxv,
                          digit_hist, tiles);
-    hipError_t se = launch_exclusive_scan(digit_hist, total, nullptr, s);
+    hipError_t se = launch_exclusive_scan(digit_hist, total, nullptr, scan_scratch, s);
     if (se != hipSuccess) return se;
     if (first && last)
       hipLaunchKernelGGL((radix_downsweep_kernel<true, true>), dim3(tiles), dim3(kSortThreads), 0, s, kin, vin, n_keys,

@@ -489,7 +489,7 @@ hipError_t launch_select(const int32_t *keys, int64_t n_fact, const int32_t *col
     stage_end(st, s);
     st = stage_begin("select_scan", s);
     if (e == hipSuccess) e = hipMemcpyAsync(seg_off, seg_count, (size_t)pl.chunks * 4, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = launch_exclusive_scan(seg_off, pl.chunks, round_total, s);
+    if (e == hipSuccess) e = launch_exclusive_scan(seg_off, pl.chunks, round_total, nullptr, s);
     stage_end(st, s);
     st = stage_begin("select_copy", s);
     if (e == hipSuccess) {

@@ -11,6 +11,7 @@ namespace {
 // threads walking the array in chunks of 8192; `total` (nullable) receives
 // the sum of all values.
 // ---------------------------------------------------------------------------
+constexpr int kHistSliceShift = 15;  // 32768 counters per LDS slice of the histogram
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 8;
 
@@ -24,12 +25,13 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
   return x;
 }
 
-__global__ __launch_bounds__(kScanThreads) void exclusive_scan_kernel(uint32_t *__restrict__ a, int64_t n,
-                                                                      uint32_t *__restrict__ total) {
+// Exclusive scan of a[0, n) in place starting from `carry`, by one workgroup;
+// returns the sum of the range (to thread 0).
+__device__ __forceinline__ uint32_t scan_range(uint32_t *__restrict__ a, int64_t n, uint32_t carry) {
   __shared__ uint32_t wave_off[kScanThreads / kWave];
   __shared__ uint32_t chunk_total;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  uint32_t carry = 0;
+  uint32_t sum = 0;
   for (int64_t base = 0; base < n; base += (int64_t)kScanThreads * kScanItems) {
     const int64_t i0 = base + (int64_t)tid * kScanItems;
     uint32_t v[kScanItems];
@@ -49,16 +51,47 @@ __global__ __launch_bounds__(kScanThreads) void exclusive_scan_kernel(uint32_t *
       if (lane == kScanThreads / kWave - 1) chunk_total = wi;
     }
     __syncthreads();
-    uint32_t run = carry + wave_off[wave] + (incl - s);
+    uint32_t run = carry + sum + wave_off[wave] + (incl - s);
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
       if (i0 + j < n) a[i0 + j] = run;
       run += v[j];
     }
-    carry += chunk_total;
+    sum += chunk_total;
     __syncthreads();
   }
-  if (total && tid == 0) *total = carry;
+  return sum;
+}
+
+__global__ __launch_bounds__(kScanThreads) void exclusive_scan_kernel(uint32_t *__restrict__ a, int64_t n,
+                                                                      uint32_t *__restrict__ total) {
+  const uint32_t sum = scan_range(a, n, 0u);
+  if (total && threadIdx.x == 0) *total = sum;
+}
+
+// Multi-workgroup form: workgroup b owns a[b * per, (b + 1) * per).
+__global__ __launch_bounds__(kScanThreads) void chunk_sum_kernel(const uint32_t *__restrict__ a, int64_t n,
+                                                                 int64_t per, uint32_t *__restrict__ sums) {
+  __shared__ uint32_t part[kScanThreads / kWave];
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  uint32_t s = 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += a[i];
+  s = wave_sum_u32(s);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kScanThreads / kWave; ++w) t += part[w];
+    sums[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void chunk_scan_kernel(uint32_t *__restrict__ a, int64_t n, int64_t per,
+                                                                  const uint32_t *__restrict__ offsets) {
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  (void)scan_range(a + lo, hi - lo, offsets[blockIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -230,10 +263,193 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Partitioned key histogram: the frequency count that starts the index build
+// (Section 3.1), run as a partitioned aggregation because the hot keys are
+// not known yet.  Pass 1 appends every key in [0, n_keys) to its workgroup's
+// segment and counts it in its slice (k >> 15); the shared plan and scatter
+// above order the keys by slice as 2-byte offsets; pass 3 counts every slice
+// in LDS and adds the counts into the histogram.
+// ---------------------------------------------------------------------------
+constexpr int kHistThreads = 1024;
+constexpr int kHistVecs = 4;
+
+__global__ __launch_bounds__(kHistThreads) void hist_split_kernel(const int32_t *__restrict__ keys, int64_t n,
+                                                                  int32_t n_keys, int32_t P, int32_t *__restrict__ seg,
+                                                                  int64_t seg_cap, uint32_t *__restrict__ seg_count,
+                                                                  uint32_t *__restrict__ hist, int32_t *flag) {
+  __shared__ uint32_t lhist[kMaxSlices + kWave + 1];  // slice counts | per-lane sinks | item count
+  for (int p = threadIdx.x; p < P + kWave + 1; p += blockDim.x) lhist[p] = 0;
+  __syncthreads();
+  ColdSink o;
+  o.count = &lhist[P + kWave];
+  o.hist = lhist;
+  o.t = 0;
+  o.wshift = kHistSliceShift;
+  o.sink = (uint32_t)P + lane_id();
+  const rsrc_t out = record_buffer(seg + (int64_t)blockIdx.x * seg_cap, (uint32_t)seg_cap);
+  const uint32_t nk = (uint32_t)n_keys;
+  bool bad = false;
+  auto put = [&](const uint32_t(&k)[4 * kHistVecs], const bool(&ok)[4 * kHistVecs]) {
+    bool in[4 * kHistVecs];
+#pragma unroll
+    for (int i = 0; i < 4 * kHistVecs; ++i) {
+      in[i] = ok[i] && k[i] < nk;
+      bad |= ok[i] && k[i] >= nk;
+    }
+    cold_append(o, k, in, [&](int i, int32_t idx) { buffer_store_record((int32_t)k[i], out, idx, 0, 0, 0); });
+  };
+  const Split4 sp = split4(keys, n);
+  {  // scalar head (block 0, lanes 0-2) and tail (last block, lanes 64-66), one slot per lane
+    int64_t i = -1;
+    if (blockIdx.x == 0 && threadIdx.x < sp.head) i = threadIdx.x;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x >= kWave && threadIdx.x - kWave < n - sp.tail)
+      i = sp.tail + threadIdx.x - kWave;
+    const uint32_t k[1] = {i >= 0 ? (uint32_t)keys[i] : 0u};
+    const bool in[1] = {i >= 0 && k[0] < nk};
+    bad |= i >= 0 && k[0] >= nk;
+    cold_append(o, k, in, [&](int, int32_t idx) { buffer_store_record((int32_t)k[0], out, idx, 0, 0, 0); });
+  }
+  const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
+  const int64_t per = (sp.nvec + gridDim.x - 1) / gridDim.x;
+  const int64_t vb = (int64_t)blockIdx.x * per < sp.nvec ? (int64_t)blockIdx.x * per : sp.nvec;
+  const int64_t ve = vb + per < sp.nvec ? vb + per : sp.nvec;
+  constexpr int64_t kTile = (int64_t)kHistThreads * kHistVecs;
+  auto unpack = [&](const i32x4(&x)[kHistVecs], uint32_t(&k)[4 * kHistVecs]) {
+#pragma unroll
+    for (int u = 0; u < kHistVecs; ++u) {
+      k[4 * u] = (uint32_t)x[u].x, k[4 * u + 1] = (uint32_t)x[u].y;
+      k[4 * u + 2] = (uint32_t)x[u].z, k[4 * u + 3] = (uint32_t)x[u].w;
+    }
+  };
+  bool all_ok[4 * kHistVecs];
+#pragma unroll
+  for (int i = 0; i < 4 * kHistVecs; ++i) all_ok[i] = true;
+  auto load_tile = [&](i32x4(&x)[kHistVecs], int64_t base) {
+#pragma unroll
+    for (int u = 0; u < kHistVecs; ++u) x[u] = load_stream4(vk + base + u * kHistThreads + threadIdx.x);
+  };
+  const int64_t full_end = vb + ((ve - vb) / kTile) * kTile;
+  i32x4 xa[kHistVecs], xb[kHistVecs];
+  uint32_t k[4 * kHistVecs];
+  int64_t base = vb;
+  if (base < full_end) load_tile(xa, base);
+  while (base < full_end) {  // unconditional prefetch: the last one re-reads the current tile
+    int64_t nxt = base + kTile;
+    load_tile(xb, nxt < full_end ? nxt : base);
+    unpack(xa, k);
+    put(k, all_ok);
+    base = nxt;
+    if (base >= full_end) break;
+    nxt = base + kTile;
+    load_tile(xa, nxt < full_end ? nxt : base);
+    unpack(xb, k);
+    put(k, all_ok);
+    base = nxt;
+  }
+  if (full_end < ve) {
+    i32x4 x[kHistVecs];
+    bool ok[4 * kHistVecs];
+#pragma unroll
+    for (int u = 0; u < kHistVecs; ++u) {
+      const int64_t vi = full_end + u * kHistThreads + threadIdx.x;
+      x[u] = vi < ve ? load_stream4(vk + vi) : i32x4{0, 0, 0, 0};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ok[4 * u + j] = vi < ve;
+    }
+    unpack(x, k);
+    put(k, ok);
+  }
+  if (bad) *flag = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) seg_count[blockIdx.x] = *o.count < seg_cap ? *o.count : (uint32_t)seg_cap;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) hist[(int64_t)p * gridDim.x + blockIdx.x] = lhist[p];
+}
+
+// Pass 3.  Within a wave the value of the first active lane is often the
+// slice's dominant key (random key order puts the hottest keys in slices of
+// their own): its lanes are added once, by one lane, with the ballot count;
+// the others add 1; lanes with nothing to add hit a sink word of their own.
+constexpr int kHistSliceVecs = 2;
+
+__device__ __forceinline__ void hist_add(uint32_t *bins, uint32_t v, bool ok) {
+  const uint32_t sink = (1u << kHistSliceShift) + lane_id();
+  const uint32_t lead = __builtin_amdgcn_readfirstlane(ok ? v : 0xFFFFFFFFu);
+  const bool dup = ok && v == lead;
+  const uint64_t m = __ballot(dup);
+  const bool first = dup && lanes_below(m) == 0;
+  const uint32_t addr = !ok ? sink : (dup ? (first ? v : sink) : v);
+  const uint32_t inc = !ok ? 0u : (dup ? (first ? (uint32_t)__popcll(m) : 0u) : 1u);
+  lds_add_u32(&bins[addr], inc);
+}
+
+__global__ __launch_bounds__(kHistThreads) void hist_slice_kernel(const uint16_t *__restrict__ locals,
+                                                                  const uint32_t *__restrict__ slice_off, int32_t P,
+                                                                  int32_t n_keys, uint32_t *__restrict__ counts) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int32_t W = 1 << kHistSliceShift;
+  uint32_t *bins = reinterpret_cast<uint32_t *>(smem);  // [W] counters | [64] sinks
+  uint32_t *soff = bins + W + kWave;
+  for (int i = threadIdx.x; i < W + kWave; i += blockDim.x) bins[i] = 0;
+  for (int p = threadIdx.x; p <= P; p += blockDim.x) soff[p] = slice_off[p];
+  __syncthreads();
+  uint32_t lo, hi;
+  balanced_share(soff, P, (uint32_t)W, blockIdx.x, gridDim.x, &lo, &hi);
+  int32_t p = lo < hi ? slice_of_item(soff, P, lo) : P;
+  const i32x4 *vl = reinterpret_cast<const i32x4 *>(locals);
+  for (uint32_t at = lo; at < hi; ++p) {
+    const uint32_t end = soff[p + 1] < hi ? soff[p + 1] : hi;
+    if (end <= at) continue;
+    const int64_t sbase = (int64_t)p << kHistSliceShift;
+    const int32_t slen = (int32_t)((int64_t)n_keys - sbase < W ? (int64_t)n_keys - sbase : W);
+    walk_items<8, kHistSliceVecs, kHistThreads, i32x4>(
+        at, end, [&](uint32_t i) { lds_add_u32(&bins[locals[i]], 1u); },
+        [&](uint32_t vi) { return load_stream4(vl + vi); },
+        [&](const i32x4(&x)[kHistSliceVecs], const bool(&valid)[kHistSliceVecs]) {
+#pragma unroll
+          for (int u = 0; u < kHistSliceVecs; ++u) {
+            const uint32_t d[4] = {(uint32_t)x[u].x, (uint32_t)x[u].y, (uint32_t)x[u].z, (uint32_t)x[u].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              hist_add(bins, d[j] & 0xFFFFu, valid[u]);
+              hist_add(bins, d[j] >> 16, valid[u]);
+            }
+          }
+        });
+    __syncthreads();
+    for (int i = threadIdx.x; i < slen; i += blockDim.x) {
+      const uint32_t c = bins[i];
+      if (c) {
+        global_add_u32(&counts[sbase + i], c);
+        bins[i] = 0;
+      }
+    }
+    __syncthreads();
+    at = end;
+  }
+}
+
 }  // namespace
 
-hipError_t launch_exclusive_scan(uint32_t *a, int64_t n, uint32_t *total, hipStream_t s) {
-  hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a, n, total);
+hipError_t launch_exclusive_scan(uint32_t *a, int64_t n, uint32_t *total, uint32_t *scratch, hipStream_t s) {
+  // With scratch (kScanBlocks + 1 words): chunk sums, one scan over them, then
+  // every chunk scanned from its offset.  Small arrays, or no scratch: one
+  // workgroup.
+  constexpr int64_t kChunk = (int64_t)kScanThreads * kScanItems;
+  if (!scratch || n <= 4 * kChunk) {
+    hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a, n, total);
+    return hipGetLastError();
+  }
+  int64_t per = (n + kScanBlocks - 1) / kScanBlocks;
+  per = (per + kChunk - 1) / kChunk * kChunk;
+  const int blocks = (int)((n + per - 1) / per);
+  hipLaunchKernelGGL(chunk_sum_kernel, dim3(blocks), dim3(kScanThreads), 0, s, a, n, per, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, scratch, (int64_t)blocks, total);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(chunk_scan_kernel, dim3(blocks), dim3(kScanThreads), 0, s, a, n, per, scratch);
   return hipGetLastError();
 }
 
@@ -264,6 +480,62 @@ hipError_t launch_partition_scatter(const SliceTables &tab, int32_t P, int32_t B
                        tab.seg_count, tab.hist, tab.slice_off, P, t, wshift, out_local, out_vals);
   }
   return hipGetLastError();
+}
+
+HistPlan hist_plan(int64_t n_fact, int32_t n_keys, const DeviceInfo &dev) {
+  HistPlan pl;
+  pl.blocks = dev.cu_count > 0 ? dev.cu_count : 256;
+  pl.slices = (int32_t)(((int64_t)n_keys + (1 << kHistSliceShift) - 1) >> kHistSliceShift);
+  pl.round = n_fact < kMaxRound ? n_fact : kMaxRound;
+  const int64_t nvec = (pl.round + 3) / 4 + 1;
+  pl.seg_cap = 4 * ((nvec + pl.blocks - 1) / pl.blocks) + 8;
+  return pl;
+}
+
+size_t hist_partition_bytes(const HistPlan &pl) {
+  auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const int32_t P = pl.slices > 0 ? pl.slices : 1;
+  return r((size_t)pl.blocks * pl.seg_cap * 4) + r((size_t)pl.round * 2 + 16) + r((size_t)P * pl.blocks * 4) +
+         r((size_t)P * 4) + r(4) + r((size_t)pl.blocks * 4) + r((size_t)(P + 1) * 4);
+}
+
+hipError_t launch_histogram_partitioned(const int32_t *keys, int64_t n_fact, int32_t n_keys, uint32_t *counts,
+                                        int32_t *flag, void *part_ws, const HistPlan &pl, hipStream_t s) {
+  auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  char *ws = (char *)part_ws;
+  int32_t *seg = (int32_t *)ws;
+  ws += r((size_t)pl.blocks * pl.seg_cap * 4);
+  uint16_t *items = (uint16_t *)ws;
+  ws += r((size_t)pl.round * 2 + 16);
+  SliceTables tab;
+  tab.hist = (uint32_t *)ws;
+  ws += r((size_t)pl.slices * pl.blocks * 4);
+  tab.row_total = (uint32_t *)ws;
+  ws += r((size_t)pl.slices * 4);
+  tab.total = (uint32_t *)ws;
+  ws += r(4);
+  tab.seg_count = (uint32_t *)ws;
+  ws += r((size_t)pl.blocks * 4);
+  tab.slice_off = (uint32_t *)ws;
+  const size_t lds3 = ((size_t)(1 << kHistSliceShift) + kWave + pl.slices + 1) * 4;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(hist_slice_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds3);
+  for (int64_t off = 0; off < n_fact; off += pl.round) {
+    const int64_t n = n_fact - off < pl.round ? n_fact - off : pl.round;
+    hipLaunchKernelGGL(hist_split_kernel, dim3(pl.blocks), dim3(kHistThreads), 0, s, keys + off, n, n_keys, pl.slices,
+                       seg, pl.seg_cap, tab.seg_count, tab.hist, flag);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_partition_plan(tab, pl.slices, pl.blocks, s);
+    if (e == hipSuccess)
+      e = launch_partition_scatter(tab, pl.slices, pl.blocks, seg, nullptr, pl.seg_cap, 0, kHistSliceShift, items,
+                                   nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(hist_slice_kernel, dim3(pl.blocks), dim3(kHistThreads), lds3, s, items, tab.slice_off,
+                       pl.slices, n_keys, counts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace skew

@@ -88,10 +88,12 @@ int device_info(skew::DeviceInfo *out) {
 
 // Workspace layouts.  The first 256 bytes always hold the query error flag.
 struct BuildWs {
-  size_t counts, keys_a, keys_b, vals_a, vals_b, hist, total;
+  size_t counts, keys_a, keys_b, vals_a, vals_b, hist, scan, part, part_bytes, total;
 };
 
-BuildWs build_ws(int32_t n_keys) {
+skew::DeviceInfo sizing_device();
+
+BuildWs build_ws(int64_t n_fact, int32_t n_keys) {
   BuildWs w;
   const size_t n4 = round_up((size_t)n_keys * 4);
   w.counts = skew::kFlagBytes;
@@ -100,7 +102,14 @@ BuildWs build_ws(int32_t n_keys) {
   w.vals_a = w.keys_b + n4;
   w.vals_b = w.vals_a + n4;
   w.hist = w.vals_b + n4;
-  w.total = w.hist + round_up((size_t)256 * 4 * (size_t)skew::sort_tiles(n_keys));
+  w.scan = w.hist + round_up((size_t)256 * 4 * (size_t)skew::sort_tiles(n_keys));
+  w.part = w.scan + round_up((size_t)(skew::kScanBlocks + 1) * 4);
+  // the partitioned histogram, for large fact columns
+  w.part_bytes = 0;
+  const skew::HistPlan pl = skew::hist_plan(n_fact, n_keys, sizing_device());
+  if (n_fact >= skew::kPartitionMinFact && pl.slices <= skew::kMaxSlices)
+    w.part_bytes = round_up(skew::hist_partition_bytes(pl));
+  w.total = w.part + w.part_bytes;
   return w;
 }
 
@@ -193,7 +202,7 @@ size_t skew_workspace_bytes(int op, int64_t n_fact, int32_t n_keys) {
   if (n_fact < 0 || n_keys < 0) return 0;
   switch (op) {
     case SKEW_OP_BUILD:
-      return build_ws(n_keys).total;
+      return build_ws(n_fact, n_keys).total;
     case SKEW_OP_JOIN:
       return join_ws(n_keys) + join_part_ws(n_fact, n_keys);
     case SKEW_OP_GROUP:
@@ -229,7 +238,7 @@ int build_skew_layout(const int32_t *fact_keys, int64_t n_fact, int32_t n_keys, 
       !aligned4(fact_recoded) || !aligned4(dim_price) || !aligned4(price_out))
     return fail(SKEW_EINVAL, "32-bit arrays must be 4-byte aligned");
   if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
-  const BuildWs w = build_ws(n_keys);
+  const BuildWs w = build_ws(n_fact, n_keys);
   if (workspace_bytes < w.total)
     return fail(SKEW_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, w.total);
 
@@ -244,7 +253,14 @@ int build_skew_layout(const int32_t *fact_keys, int64_t n_fact, int32_t n_keys, 
   skew::StageTimer st = skew::stage_begin("build_histogram", s);
   hipError_t e = skew::launch_fill_u32((uint32_t *)flag, 1, 0u, s);
   if (e == hipSuccess) e = skew::launch_fill_u32(counts, n_keys, 0u, s);
-  if (e == hipSuccess) e = skew::launch_histogram(fact_keys, n_fact, n_keys, counts, flag, dev, s);
+  if (e == hipSuccess) {
+    const skew::DeviceInfo pdev = part_device(dev);
+    const skew::HistPlan pl = skew::hist_plan(n_fact, n_keys, pdev);
+    if (w.part_bytes > 0 && skew::hist_partition_bytes(pl) <= w.part_bytes)
+      e = skew::launch_histogram_partitioned(fact_keys, n_fact, n_keys, counts, flag, ws + w.part, pl, s);
+    else
+      e = skew::launch_histogram(fact_keys, n_fact, n_keys, counts, flag, dev, s);
+  }
   skew::stage_end(st, s);
   if (e != hipSuccess) return hip_fail(e, "histogram launch");
   int32_t bad = 0;
@@ -257,7 +273,7 @@ int build_skew_layout(const int32_t *fact_keys, int64_t n_fact, int32_t n_keys, 
   st = skew::stage_begin("build_rank_sort", s);
   e = skew::launch_rank_sort(counts, n_keys, n_fact, perm, counts_by_rank, (uint32_t *)(ws + w.keys_a),
                              (uint32_t *)(ws + w.keys_b), (int32_t *)(ws + w.vals_a), (int32_t *)(ws + w.vals_b),
-                             (uint32_t *)(ws + w.hist), s);
+                             (uint32_t *)(ws + w.hist), (uint32_t *)(ws + w.scan), s);
   skew::stage_end(st, s);
   st = skew::stage_begin("build_inverse", s);
   if (e == hipSuccess) e = skew::launch_inverse(perm, n_keys, rank, s);

@@ -333,6 +333,81 @@ def pin_heavy_hitters(orc, seeds=range(10)):
     assert (keys == L.perm[:50]).all() and (counts == L.counts_by_rank[:50]).all()
 
 
+# ---------------------------------------------------------------------------
+# Stack-distance cache model (Section 3.4)
+# ---------------------------------------------------------------------------
+def lru_hit_rate(f, S, n, seed):
+    """Exact LRU cache of S lines fed n i.i.d. accesses drawn from f (hits after a warm-up fifth)."""
+    import collections
+
+    rng = np.random.default_rng(seed)
+    acc = rng.choice(f.size, size=n, p=f)
+    cache = collections.OrderedDict()
+    hits = 0
+    warm = n // 5
+    for t, a in enumerate(acc.tolist()):
+        if a in cache:
+            cache.move_to_end(a)
+            hits += t >= warm
+        else:
+            cache[a] = None
+            if len(cache) > S:
+                cache.popitem(last=False)
+    return hits / (n - warm)
+
+
+def pin_cache_model(orc):
+    # uniform lines: no line repeats before S trials, so K = S and the rate is 1 - (1 - 1/L)^S
+    for L, S in ((50, 1), (50, 7), (1000, 100), (1000, 999)):
+        f = np.full(L, 1.0 / L)
+        assert abs(orc.cache_model(f, S) - (1 - (1 - 1 / L) ** S)) < 1e-12, (L, S)
+    # one hot line h and L - 1 equal cold lines c: for the hot line no other line repeats before
+    # L - 1 trials, so K = S; for a cold line the hot line repeats from k > (1 - c) / h on, so
+    # d(k) = k (1 - a) + 1 with a = h / (1 - c) and K = ceil((S - 1) / (1 - a))
+    for L, h, S in ((1000, 0.3, 100), (500, 0.05, 40), (2000, 0.6, 300)):
+        c = (1 - h) / (L - 1)
+        a = h / (1 - c)
+        K = max(S, int(np.ceil((S - 1) / (1 - a))))
+        assert (1 - c) / h < K < L - 1
+        want = h * (1 - (1 - h) ** S) + (1 - h) * (1 - (1 - c) ** K)
+        f = np.concatenate([[h], np.full(L - 1, c)])
+        assert abs(orc.cache_model(f, S) - want) < 1e-9, (L, h, S)
+    # two hot lines h1, h2 and L - 2 equal cold lines c: seen from line 1 the other hot line repeats
+    # once k h2 / (1 - h1) > 1, so d(k) = k (1 - h2 / (1 - h1)) + 1; from line 2 likewise; from a
+    # cold line both hot lines repeat, d(k) = k (1 - (h1 + h2) / (1 - c)) + 2
+    L, h1, h2, S = 1000, 0.5, 0.3, 50
+    c = (1 - h1 - h2) / (L - 2)
+    K1 = int(np.ceil((S - 1) / (1 - h2 / (1 - h1))))
+    K2 = int(np.ceil((S - 1) / (1 - h1 / (1 - h2))))
+    Kc = int(np.ceil((S - 2) / (1 - (h1 + h2) / (1 - c))))
+    assert max(K1, K2, Kc) < (1 - c) / c / 2
+    want = h1 * (1 - (1 - h1) ** K1) + h2 * (1 - (1 - h2) ** K2) + (L - 2) * c * (1 - (1 - c) ** Kc)
+    f = np.concatenate([[h1, h2], np.full(L - 2, c)])
+    assert abs(orc.cache_model(f, S) - want) < 1e-9
+    # a cache that holds every line, or a single line, always hits
+    f = np.array([0.5, 0.25, 0.125, 0.125])
+    assert abs(orc.cache_model(f, 4) - 1.0) < 1e-12
+    assert abs(orc.cache_model(np.array([1.0]), 1) - 1.0) < 1e-12
+    # zero-frequency lines change nothing
+    g = np.concatenate([f, np.zeros(5)])
+    assert abs(orc.cache_model(g, 2) - orc.cache_model(f, 2)) < 1e-12
+    # the hit rate grows with the cache
+    rng = np.random.default_rng(3)
+    r = np.arange(1, 401, dtype=np.float64) ** -1.0
+    z = (r / r.sum())[rng.permutation(400)]
+    rates = [orc.cache_model(z, S) for S in (1, 5, 20, 80, 200)]
+    assert all(a < b for a, b in zip(rates, rates[1:]))
+    # within the paper's 5 % of an exact LRU simulation for caches up to a tenth of the lines
+    for s in (0.0, 0.5, 1.0, 1.5):
+        L = 1500
+        r = np.arange(1, L + 1, dtype=np.float64) ** -s
+        f = (r / r.sum())[np.random.default_rng(7).permutation(L)]
+        for S in (15, 150):
+            m = orc.cache_model(f, S)
+            sim = lru_hit_rate(f, S, 60_000, 11)
+            assert abs(m - sim) < 0.05, (s, S, m, sim)
+
+
 ALL_PINS = [pin_fk_bruteforce, pin_fk_special_cases, pin_group_bruteforce, pin_layout_bruteforce, pin_fig2,
             pin_layout_invariants, pin_invariance_all_layouts, pin_stale_layout, pin_materialize, pin_select,
-            pin_heavy_hitters]
+            pin_heavy_hitters, pin_cache_model]

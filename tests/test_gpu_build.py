@@ -1,0 +1,106 @@
+"""GPU parity of the index build at sizes that take the partitioned key histogram.
+
+Fact columns of at least 2^22 keys are counted by partitioning the keys into
+slices of 32768 key ids and counting each slice in LDS; the layout (perm,
+rank, frequencies, recoded facts, permuted dimension) must equal the oracle's
+byte for byte: several rounds of 2^28 keys, key domains that are not a
+multiple of the slice, unaligned columns, out-of-range keys, and a domain too
+large for the slice table (the hash-privatised count).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1910_10063_amd import skew
+from paper_1910_10063_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def check(L, ref):
+    assert (host(L.perm) == ref.perm).all(), "perm"
+    assert (host(L.rank) == ref.rank).all(), "rank"
+    assert (host(L.counts_by_rank).astype(np.int64) == ref.counts_by_rank).all(), "counts_by_rank"
+    if L.fact_recoded is not None:
+        assert (host(L.fact_recoded) == ref.fact_recoded).all(), "fact_recoded"
+    if L.price is not None:
+        assert (host(L.price) == ref.price).all(), "price"
+
+
+@pytest.mark.parametrize("N,s", [(1_000_003, 1.0), (32768, 0.5), (65537, 1.5), (5_000_000, 0.0), (1, 0.0)])
+def test_partitioned_build(N, s):
+    F = (1 << 22) + 12_345
+    say(f"build N={N} F={F} s={s}")
+    h = W.host_join_inputs(5, N, F, s)
+    ref = oracle.build_layout(h["fact"], N, h["price"], h["category"])
+    L = skew.build_skew_layout(to_dev(h["fact"]), N, to_dev(h["price"]), to_dev(h["category"]))
+    check(L, ref)
+
+
+@pytest.mark.parametrize("offset", [1, 2, 3])
+def test_partitioned_build_unaligned(offset):
+    N, F = 200_000, (1 << 22) + 3
+    say(f"build unaligned offset={offset}")
+    h = W.host_join_inputs(6, N, F + offset, 1.0)
+    fact = h["fact"][offset:]
+    ref = oracle.build_layout(fact, N, h["price"], h["category"])
+    buf = to_dev(h["fact"])
+    L = skew.build_skew_layout(buf[offset:], N, to_dev(h["price"]), to_dev(h["category"]))
+    check(L, ref)
+
+
+def test_partitioned_build_out_of_range():
+    N, F = 100_000, 1 << 22
+    say("build partitioned out-of-range keys")
+    rng = np.random.default_rng(9)
+    fact = rng.integers(0, N, F).astype(np.int32)
+    for bad in (N, -1, 2**31 - 1):
+        f = fact.copy()
+        f[F // 2] = bad
+        with pytest.raises(skew.SkewError) as e:
+            skew.build_skew_layout(to_dev(f), N)
+        assert e.value.code == skew.SKEW_ERANGE
+
+
+def test_large_domain_uses_hash_count():
+    """More than 1024 slices of 32768 keys: the hash-privatised count takes over."""
+    N, F = 40_000_000, (1 << 22) + 1
+    say(f"build large domain N={N} F={F}")
+    rng = np.random.default_rng(10)
+    fact = rng.integers(0, N, F).astype(np.int32)
+    ref = oracle.build_layout(fact, N)
+    L = skew.build_skew_layout(to_dev(fact), N)
+    check(L, ref)
+
+
+@pytest.mark.slow
+def test_partitioned_build_three_rounds():
+    """2^29 + 7 Zipf(1.0) keys over 1e7 rows: three rounds of the partitioned count."""
+    N, F = 10_000_000, (1 << 29) + 7
+    say(f"build three rounds N={N} F={F}")
+    d = W.device_join_inputs(7, N, F, 1.0, DEV)
+    L = skew.build_skew_layout(d["fact"], N, d["price"], d["category"])
+    fact = host(d["fact"])
+    ref = oracle.build_layout(fact, N, host(d["price"]), host(d["category"]))
+    check(L, ref)
+    del d, L
+    torch.cuda.empty_cache()

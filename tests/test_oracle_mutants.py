@@ -35,6 +35,9 @@ MUTANTS = {
     "select_key_not_offset": ("    if (col[k] < lt) out[n++] = j;", "    if (col[k] < lt) out[n++] = k;"),
     "heavy_ascending": ("  qsort(e, (size_t)n_keys, sizeof(freq_entry), by_decreasing_frequency);\n  for (int32_t r = 0; r < k; ++r) {\n    keys[r] = e[r].key;",
                         "  qsort(e, (size_t)n_keys, sizeof(freq_entry), by_decreasing_frequency);\n  for (int32_t r = 0; r < k; ++r) {\n    keys[r] = e[n_keys - 1 - r].key;"),
+    "model_no_repeat_term": ("    if (n > 1.0) rep += n - 1.0;", "    if (n > 1.0) rep += n;"),
+    "model_cdf_exponent": ("hit += f[i] * (1.0 - pow(1.0 - f[i], (double)lo));", "hit += f[i] * (1.0 - pow(1.0 - f[i], (double)S));"),
+    "model_scale_dropped": ("  const double scale = k / (1.0 - f[i]);", "  const double scale = k;"),
     "heavy_counts_invalid": ("    if (g >= 0 && g < n_keys) e[g].cnt += 1;", "    if (g >= 0 && g < n_keys) e[g].cnt += 1;\n    else if (g == n_keys && n_keys > 0) e[0].cnt += 1;"),
 }
 
