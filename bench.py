@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline query only (for profiler runs)")
     ap.add_argument("--with-group", action="store_true", help="run the group-by workload even with --no-extras")
     ap.add_argument("--with-ops", action="store_true", help="run the operator variants even with --no-extras")
+    ap.add_argument("--model-validation", action="store_true",
+                    help="only the cache-model check: single-pass queries without LDS prefix on both layouts "
+                         "(3 skew, then 3 identity) for an L2 hit-rate profile, and the model's predictions")
     ap.add_argument("--skew-only", action="store_true",
                     help="skip the identity-layout query (profiler runs: one kernel name per stage)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -132,6 +135,18 @@ def main():
 
     log("layout build")
     build_ms = timed(build, 3, 1, stream)
+
+    cache_model = bench_cache_model(cbr, rank, N, F, dev)
+    if args.model_validation:
+        sws = skew.workspace(skew.SKEW_OP_JOIN_SINGLE_PASS, F, N, dev)
+        o = (torch.empty(16, dtype=torch.int64, device=dev), torch.empty(16, dtype=torch.int64, device=dev))
+        for keys, pr, ca in ((Cp, pp, cp), (C, price, cat)):
+            for _ in range(3):
+                skew.fk_join_aggregate(keys, pr, ca, 16, True, hot_rows=0, ws=sws, out=o)
+        torch.cuda.synchronize()
+        print(json.dumps({"cache_model": cache_model, "n_fact": F, "n_rows": N, "zipf_s": S,
+                          "dispatches": "join_kernel<16>: 3 skew layout, then 3 identity layout, hot_rows=0"}))
+        return
 
     # ---- queries
     jws = skew.workspace(skew.SKEW_OP_JOIN, F, N, dev)
@@ -234,6 +249,7 @@ def main():
         "stages_ms": {"skew": stages_skew, "identity": stages_ident, "build": per_query(st_build, 1)},
         "build": {"ms": build_ms, "fact_tuples_per_s": F / (build_ms * 1e-3)},
         "layouts_agree": agree,
+        "cache_model": cache_model,
     }
 
     if not args.no_extras:
@@ -328,6 +344,27 @@ def bench_group_by(K, WU, dev, stream):
             "roofline_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "stages_ms": stages,
             "build_s_incl_sync": build_s,
             "layouts_agree": len({r["sum_digest"] for r in res.values()}) == 1}
+
+
+def bench_cache_model(cbr, rank, N, F, dev):
+    """Section 3.4's model for the dimension lookups: 128-byte lines of 32 values, one XCD's 4 MB L2
+    (32768 lines; each XCD sees the whole access distribution) and the 256 MB memory-side cache."""
+    import torch
+
+    from paper_1910_10063_amd import skew
+
+    ws = skew.workspace(skew.SKEW_OP_CACHE_MODEL, 0, N, dev)
+    t0 = time.time()
+    out = {"values_per_line": 32}
+    for name, S in (("l2", 32768), ("mall", 2_097_152)):
+        out[f"{name}_lines"] = S
+        out[f"{name}_hit_skew"] = skew.cache_model_hit_rate(cbr, S, 32, ws=ws)
+        out[f"{name}_hit_identity"] = skew.cache_model_hit_rate(cbr, S, 32, rank=rank, ws=ws)
+    out["seconds_for_4_evaluations"] = round(time.time() - t0, 3)
+    t = min(skew.max_hot_rows(True), N)
+    out["lds_prefix_rows"] = t
+    out["lds_prefix_share"] = float(cbr[:t].to(torch.int64).sum().item()) / F
+    return out
 
 
 def bench_operators(K, C, price, Cp, pp, perm, N, F, dev, stream):

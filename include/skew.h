@@ -54,6 +54,7 @@ extern "C" {
 #define SKEW_OP_MATERIALIZE 6
 #define SKEW_OP_SELECT 7
 #define SKEW_OP_HEAVY 8
+#define SKEW_OP_CACHE_MODEL 9 /* n_keys = keys; sized for lines of 1 value (the largest need) */
 
 /* hot_rows / hot_groups special values. */
 #define SKEW_HOT_AUTO (-1)  /* library picks the hot prefix from LDS capacity */
@@ -220,6 +221,31 @@ int select_fact_rows(const int32_t *fact_keys, int64_t n_fact, const int32_t *di
 int heavy_hitter_counts(const int32_t *ranked_keys, int64_t n_fact, int32_t n_keys, int32_t k, const int32_t *perm,
                         int32_t *out_keys, int64_t *out_count, void *workspace, size_t workspace_bytes,
                         void *stream);
+
+/*
+ * cache_model_hit_rate - the stack-distance cache model of Section 3.4: the
+ * hit rate an LRU cache of cache_lines lines is expected to reach on the
+ * dimension lookups of a fact column, for a given layout.  Line frequencies
+ * come from the key frequencies (Section 3.4: with the frequency-ordered
+ * layout the most frequent line holds the v most frequent values); for line
+ * i the model finds the number of trials K_i after which S other distinct
+ * lines are expected, and sums f_i (1 - (1 - f_i)^K_i).
+ *
+ *   counts_by_rank[n_keys]  uint32 frequencies in rank order (build_skew_layout).
+ *   rank[n_keys]            nullable.  NULL: the frequency-ordered layout (line i
+ *                           holds ranks [i v, (i + 1) v)).  Else the identity
+ *                           layout: line i holds keys [i v, (i + 1) v), key k
+ *                           occurring counts_by_rank[rank[k]] times.
+ *   values_per_line         v >= 1 (32 for 128-byte lines of 4-byte values).
+ *   cache_lines             S >= 1.
+ *   out_hit                 HOST double: the modelled hit rate (0 with no lookups).
+ *   workspace               >= skew_workspace_bytes(SKEW_OP_CACHE_MODEL, 0, n_keys).
+ *
+ * The sum of frequencies must be below 2^32.  The call waits for the stream.
+ */
+int cache_model_hit_rate(const uint32_t *counts_by_rank, int32_t n_keys, const int32_t *rank,
+                         int32_t values_per_line, int64_t cache_lines, double *out_hit, void *workspace,
+                         size_t workspace_bytes, void *stream);
 
 /*
  * skew_query_status - wait for `stream`, then report whether the last query

@@ -63,6 +63,8 @@ def bind(path: str):
     lib.oracle_heavy_hitters.restype = I32
     lib.oracle_cache_model.argtypes = [P, I64, I64]
     lib.oracle_cache_model.restype = ctypes.c_double
+    lib.oracle_star_join.argtypes = [P, P, I64, P, P, I32, P, I32, I32, P, P]
+    lib.oracle_star_join.restype = None
     return lib
 
 
@@ -75,9 +77,7 @@ def use_library(path: str | None):
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        _lib = bind(LIB)
+        _lib = bind(build())  # rebuilt when oracle.c is newer than the library
     return _lib
 
 
@@ -175,6 +175,21 @@ def heavy_hitters(G, n_keys: int, k: int):
     counts = np.empty(max(min(k, n_keys), 1), dtype=np.int64)
     kk = _load().oracle_heavy_hitters(_p(G), G.size, n_keys, int(k), _p(keys), _p(counts))
     return keys[:kk].copy(), counts[:kk].copy()
+
+
+def star_join(P, U, price, category, cust_attr, cust_lt: int):
+    """(sum, count) int64[16]: SUM(price), COUNT(*) by product category over rows whose customer passes."""
+    P = _c(P, np.int32)
+    U = _c(U, np.int32)
+    price = _c(price, np.int32)
+    category = _c(category, np.int8)
+    cust_attr = _c(cust_attr, np.int8)
+    assert P.size == U.size and price.size == category.size
+    s = np.zeros(16, dtype=np.int64)
+    c = np.zeros(16, dtype=np.int64)
+    _load().oracle_star_join(_p(P), _p(U), P.size, _p(price), _p(category), price.size, _p(cust_attr), cust_attr.size,
+                             int(cust_lt), _p(s), _p(c))
+    return s, c
 
 
 def cache_model(f, cache_lines: int) -> float:

@@ -300,3 +300,30 @@ double oracle_cache_model(const double *f, int64_t L, int64_t S) {
   }
   return hit;
 }
+
+/*
+ * Star join of one fact table with two dimensions: the FK join-aggregate of
+ * Section 1 with a second dimension that filters (the batched star-join
+ * workload).  Fact row j has a product key P[j] and a customer key U[j]; it
+ * qualifies when cust_attr[U[j]] < cust_lt (signed 8-bit compare) and then
+ * adds price[P[j]] and 1 to group category[P[j]]; rows whose category lies
+ * outside [0, 16) belong to no group, and keys outside their dimension join
+ * nothing.  sum and count have 16 entries.
+ */
+void oracle_star_join(const int32_t *P, const int32_t *U, int64_t n, const int32_t *price, const int8_t *category,
+                      int32_t n_prod, const int8_t *cust_attr, int32_t n_cust, int32_t cust_lt, int64_t *sum,
+                      int64_t *count) {
+  for (int g = 0; g < 16; ++g) {
+    sum[g] = 0;
+    count[g] = 0;
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    const int32_t p = P[j], u = U[j];
+    if (p < 0 || p >= n_prod || u < 0 || u >= n_cust) continue;
+    if (!(cust_attr[u] < cust_lt)) continue;
+    const int32_t g = category[p];
+    if (g < 0 || g >= 16) continue;
+    sum[g] += (int64_t)price[p];
+    count[g] += 1;
+  }
+}

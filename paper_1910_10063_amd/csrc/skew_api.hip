@@ -214,6 +214,8 @@ size_t skew_workspace_bytes(int op, int64_t n_fact, int32_t n_keys) {
     case SKEW_OP_MATERIALIZE:
     case SKEW_OP_HEAVY:
       return skew::kFlagBytes;
+    case SKEW_OP_CACHE_MODEL:
+      return skew::kFlagBytes + round_up(skew::model_workspace_bytes(n_keys, 1));
     case SKEW_OP_SELECT:
       return skew::kFlagBytes + round_up(skew::select_workspace_bytes(n_fact, n_keys, kPartBlocks));
     default:
@@ -443,6 +445,27 @@ int heavy_hitter_counts(const int32_t *ranked_keys, int64_t n_fact, int32_t n_ke
       skew::launch_heavy(ranked_keys, n_fact, n_keys, k, perm, out_keys, out_count, (int32_t *)workspace, dev, s);
   if (e != hipSuccess) return hip_fail(e, "heavy hitter launch");
   if (check_enabled()) return read_flag(workspace, s);
+  return ok();
+}
+
+int cache_model_hit_rate(const uint32_t *counts_by_rank, int32_t n_keys, const int32_t *rank,
+                         int32_t values_per_line, int64_t cache_lines, double *out_hit, void *workspace,
+                         size_t workspace_bytes, void *stream) {
+  if (n_keys < 1) return fail(SKEW_EINVAL, "n_keys must be >= 1");
+  if (!counts_by_rank || !out_hit) return fail(SKEW_EINVAL, "counts_by_rank and out_hit are required");
+  if (values_per_line < 1) return fail(SKEW_EINVAL, "values_per_line must be >= 1");
+  if (cache_lines < 1) return fail(SKEW_EINVAL, "cache_lines must be >= 1");
+  if (!workspace) return fail(SKEW_EINVAL, "workspace is NULL");
+  if (!aligned4(counts_by_rank) || !aligned4(rank)) return fail(SKEW_EINVAL, "32-bit arrays must be 4-byte aligned");
+  if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = skew::kFlagBytes + round_up(skew::model_workspace_bytes(n_keys, values_per_line));
+  if (workspace_bytes < need) return fail(SKEW_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const hipError_t e = skew::launch_cache_model(counts_by_rank, n_keys, rank, values_per_line, cache_lines,
+                                                (char *)workspace + skew::kFlagBytes, out_hit, dev,
+                                                (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "cache model");
   return ok();
 }
 

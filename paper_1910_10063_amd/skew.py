@@ -31,13 +31,15 @@ SKEW_OP_GROUP_SINGLE_PASS = 5
 SKEW_OP_MATERIALIZE = 6
 SKEW_OP_SELECT = 7
 SKEW_OP_HEAVY = 8
+SKEW_OP_CACHE_MODEL = 9
 
 SKEW_HOT_AUTO = -1
 SKEW_HOT_NONE = -2
 
 EXPORTED = ("skew_last_error", "skew_workspace_bytes", "build_skew_layout", "fk_join_aggregate", "group_aggregate",
             "skew_query_status", "skew_profile_enable", "skew_profile_report", "skew_max_hot_rows",
-            "skew_max_hot_groups", "materialize_column", "select_fact_rows", "heavy_hitter_counts", "skew_max_hot")
+            "skew_max_hot_groups", "materialize_column", "select_fact_rows", "heavy_hitter_counts", "skew_max_hot",
+            "cache_model_hit_rate")
 
 
 class SkewError(RuntimeError):
@@ -84,6 +86,8 @@ def load_library(path: str = LIB_PATH):
     lib.select_fact_rows.restype = ctypes.c_int
     lib.heavy_hitter_counts.argtypes = [P, I64, I32, I32, P, P, P, P, SZ, P]
     lib.heavy_hitter_counts.restype = ctypes.c_int
+    lib.cache_model_hit_rate.argtypes = [P, I32, P, I32, I64, P, P, SZ, P]
+    lib.cache_model_hit_rate.restype = ctypes.c_int
     lib.skew_max_hot.argtypes = [ctypes.c_int]
     lib.skew_max_hot.restype = I64
     if path == LIB_PATH:
@@ -265,6 +269,22 @@ def heavy_hitter_counts(ranked_keys: torch.Tensor, n_keys: int, k: int, perm: to
     _check(lib.heavy_hitter_counts(_ptr(ranked_keys), ranked_keys.numel(), n_keys, int(k), _ptr(perm), _ptr(keys),
                                    _ptr(counts), _ptr(ws), ws.numel(), _stream(dev)))
     return keys[:k], counts[:k]
+
+
+def cache_model_hit_rate(counts_by_rank: torch.Tensor, cache_lines: int, values_per_line: int = 32,
+                         rank: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> float:
+    """Hit rate of the stack-distance model (Section 3.4); rank=None: frequency-ordered layout."""
+    lib = load_library()
+    _need(counts_by_rank, torch.int32, "counts_by_rank")
+    if rank is not None:
+        _need(rank, torch.int32, "rank")
+    dev = counts_by_rank.device
+    if ws is None:
+        ws = workspace(SKEW_OP_CACHE_MODEL, 0, counts_by_rank.numel(), dev)
+    out = ctypes.c_double(0.0)
+    _check(lib.cache_model_hit_rate(_ptr(counts_by_rank), counts_by_rank.numel(), _ptr(rank), int(values_per_line),
+                                    int(cache_lines), ctypes.byref(out), _ptr(ws), ws.numel(), _stream(dev)))
+    return out.value
 
 
 def max_hot(op: int) -> int:

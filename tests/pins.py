@@ -408,6 +408,55 @@ def pin_cache_model(orc):
             assert abs(m - sim) < 0.05, (s, S, m, sim)
 
 
+# ---------------------------------------------------------------------------
+# Star join (two dimensions, batched star-join workload)
+# ---------------------------------------------------------------------------
+def pin_star_join(orc, seeds=range(10)):
+    for seed in seeds:
+        rng = np.random.default_rng(600 + seed)
+        n_p, n_c = int(rng.integers(1, 7)), int(rng.integers(1, 6))
+        f = int(rng.integers(0, 25))
+        price = rng.integers(-100, 10000, n_p).astype(np.int32)
+        cat = rng.integers(-2, 18, n_p).astype(np.int8)
+        attr = rng.integers(-5, 100, n_c).astype(np.int8)
+        P = rng.integers(-1, n_p + 1, f).astype(np.int32)
+        U = rng.integers(-1, n_c + 1, f).astype(np.int32)
+        prod = [(int(k), int(price[k]), int(cat[k])) for k in rng.permutation(n_p)]
+        cust = [(int(k), int(attr[k])) for k in rng.permutation(n_c)]
+        for lt in (-128, 0, 30, 127):
+            s = [0] * 16
+            c = [0] * 16
+            for pk, uk in zip(P.tolist(), U.tolist()):
+                for ck, a in cust:
+                    if ck != uk or not (a < lt):
+                        continue
+                    for key, pr, g in prod:
+                        if key == pk and 0 <= g < 16:
+                            s[g] += pr
+                            c[g] += 1
+            gs, gc = orc.star_join(P, U, price, cat, attr, lt)
+            assert gs.tolist() == s and gc.tolist() == c, (seed, lt)
+    # a customer filter that every row passes reduces to the one-dimension join grouped by category
+    rng = np.random.default_rng(61)
+    n_p, n_c, F = 300, 50, 4000
+    price = rng.integers(1, 10001, n_p).astype(np.int32)
+    cat = rng.integers(0, 16, n_p).astype(np.int8)
+    attr = rng.integers(0, 100, n_c).astype(np.int8)
+    P = rng.integers(0, n_p, F).astype(np.int32)
+    U = rng.integers(0, n_c, F).astype(np.int32)
+    s1, c1 = orc.star_join(P, U, price, cat, attr, 100)
+    s2, c2 = orc.fk_join_aggregate(P, price, cat, 16, True)
+    assert (s1 == s2).all() and (c1 == c2).all()
+    # recoding both key columns through their layouts (union histograms) changes no answer (Section 3.2)
+    Lp = orc.build_layout(P, n_p, price, cat)
+    Lc = orc.build_layout(U, n_c)
+    attr_n = orc.permute_dim(attr, Lc.perm)
+    for lt in (10, 50):
+        a = orc.star_join(P, U, price, cat, attr, lt)
+        b = orc.star_join(Lp.fact_recoded, Lc.fact_recoded, Lp.price, Lp.category, attr_n, lt)
+        assert (a[0] == b[0]).all() and (a[1] == b[1]).all()
+
+
 ALL_PINS = [pin_fk_bruteforce, pin_fk_special_cases, pin_group_bruteforce, pin_layout_bruteforce, pin_fig2,
             pin_layout_invariants, pin_invariance_all_layouts, pin_stale_layout, pin_materialize, pin_select,
-            pin_heavy_hitters, pin_cache_model]
+            pin_heavy_hitters, pin_cache_model, pin_star_join]

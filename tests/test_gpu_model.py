@@ -1,0 +1,89 @@
+"""The stack-distance cache model of Section 3.4 on the device against the oracle.
+
+Both evaluate the same model in fp64 (the device with sorted line counts and
+prefix sums, the oracle with direct sums); the tolerance covers a search that
+lands one trial apart at a rounding boundary, which moves line i's term by at
+most 0.54 / K_i^2 <= 0.54 / S^2, and fp64 summation order.  The model itself
+is not pinned to the paper (it prints no model output); the oracle is pinned
+to closed forms and to an LRU simulation in tests/pins.py.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1910_10063_amd import skew
+from paper_1910_10063_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module", params=[(3000, 1.0), (50_000, 0.5), (100_000, 1.0)], ids=str)
+def layout(request):
+    N, s = request.param
+    F = 1_000_000
+    say(f"cache model layout N={N} F={F} s={s}")
+    h = W.host_join_inputs(1, N, F, s)
+    L = skew.build_skew_layout(torch.from_numpy(h["fact"]).to(DEV), N)
+    cbr = host(L.counts_by_rank).astype(np.int64)
+    rank = host(L.rank)
+    return dict(N=N, L=L, cbr=cbr, rank=rank)
+
+
+@pytest.mark.parametrize("S", [1, 37, 512, 3000, 100_000])
+@pytest.mark.parametrize("which", ["skew", "identity"])
+def test_model_matches_oracle(layout, S, which):
+    N, L, cbr, rank = layout["N"], layout["L"], layout["cbr"], layout["rank"]
+    v = 1 if N <= 3000 else 32
+    say(f"cache model N={N} v={v} S={S} {which}")
+    if which == "skew":
+        got = skew.cache_model_hit_rate(L.counts_by_rank, S, values_per_line=v)
+        f = oracle.line_frequencies(cbr, v)
+    else:
+        got = skew.cache_model_hit_rate(L.counts_by_rank, S, values_per_line=v, rank=L.rank)
+        f = oracle.line_frequencies(cbr[rank], v)
+    want = oracle.cache_model(f, S)
+    assert abs(got - want) < 1e-6, (got, want)
+
+
+@pytest.mark.parametrize("L_,S", [(1000, 1), (1000, 100), (1000, 999), (1000, 1000), (70_000, 4096)])
+def test_model_uniform_closed_form(L_, S):
+    say(f"cache model uniform L={L_} S={S}")
+    counts = torch.full((L_,), 7, dtype=torch.int32, device=DEV)
+    got = skew.cache_model_hit_rate(counts, S, values_per_line=1)
+    want = 1.0 if S >= L_ else 1 - (1 - 1 / L_) ** S
+    assert abs(got - want) < 1e-9
+
+
+def test_model_edges():
+    say("cache model edges")
+    z = torch.zeros(100, dtype=torch.int32, device=DEV)
+    assert skew.cache_model_hit_rate(z, 10, values_per_line=4) == 0.0
+    one = torch.zeros(100, dtype=torch.int32, device=DEV)
+    one[0] = 5
+    assert abs(skew.cache_model_hit_rate(one, 1, values_per_line=1) - 1.0) < 1e-12
+    # the frequency-ordered layout never does worse than the identity layout on a skewed column
+    rng = np.random.default_rng(4)
+    c = np.sort((rng.zipf(1.3, 20_000) % 5000))[::-1]
+    cnt = np.bincount(c, minlength=5000).astype(np.int64)
+    order = np.lexsort((np.arange(5000), -cnt))
+    cbr = torch.from_numpy(cnt[order].astype(np.int32)).to(DEV)
+    rank = np.empty(5000, np.int32)
+    rank[order] = np.arange(5000, dtype=np.int32)
+    sk = skew.cache_model_hit_rate(cbr, 50, values_per_line=16)
+    idn = skew.cache_model_hit_rate(cbr, 50, values_per_line=16, rank=torch.from_numpy(rank).to(DEV))
+    assert sk >= idn

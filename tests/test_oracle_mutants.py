@@ -38,6 +38,9 @@ MUTANTS = {
     "model_no_repeat_term": ("    if (n > 1.0) rep += n - 1.0;", "    if (n > 1.0) rep += n;"),
     "model_cdf_exponent": ("hit += f[i] * (1.0 - pow(1.0 - f[i], (double)lo));", "hit += f[i] * (1.0 - pow(1.0 - f[i], (double)S));"),
     "model_scale_dropped": ("  const double scale = k / (1.0 - f[i]);", "  const double scale = k;"),
+    "star_filter_inverted": ("    if (!(cust_attr[u] < cust_lt)) continue;", "    if (cust_attr[u] < cust_lt) continue;"),
+    "star_customer_as_product": ("    const int32_t g = category[p];\n    if (g < 0 || g >= 16) continue;\n    sum[g] += (int64_t)price[p];",
+                                 "    const int32_t g = category[p];\n    if (g < 0 || g >= 16) continue;\n    sum[g] += (int64_t)price[u < n_prod ? u : p];"),
     "heavy_counts_invalid": ("    if (g >= 0 && g < n_keys) e[g].cnt += 1;", "    if (g >= 0 && g < n_keys) e[g].cnt += 1;\n    else if (g == n_keys && n_keys > 0) e[0].cnt += 1;"),
 }
 
