@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline query only (for profiler runs)")
     ap.add_argument("--with-group", action="store_true", help="run the group-by workload even with --no-extras")
     ap.add_argument("--with-ops", action="store_true", help="run the operator variants even with --no-extras")
+    ap.add_argument("--with-star", action="store_true", help="run the batched star join even with --no-extras")
+    ap.add_argument("--with-serve", action="store_true", help="run the serving loop even with --no-extras")
+    ap.add_argument("--serve-seconds", type=float, default=40.0, help="length of the serving run (0: skip)")
     ap.add_argument("--model-validation", action="store_true",
                     help="only the cache-model check: single-pass queries without LDS prefix on both layouts "
                          "(3 skew, then 3 identity) for an L2 hit-rate profile, and the model's predictions")
@@ -287,6 +290,10 @@ def main():
         result["zipf_sweep"] = sweep_s
     if not args.no_extras or args.with_ops:
         result["operators"] = bench_operators(K, C, price, Cp, pp, perm, N, F, dev, stream)
+    if not args.no_extras or args.with_star:
+        result["star_batch"] = bench_star(K, dev, stream)
+    if (not args.no_extras or args.with_serve) and args.serve_seconds > 0:
+        result["serving"] = bench_serve(args.serve_seconds, dev)
     if not args.no_extras or args.with_group:
         result["group_by"] = bench_group_by(K, WU, dev, stream)
 
@@ -344,6 +351,117 @@ def bench_group_by(K, WU, dev, stream):
             "roofline_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "stages_ms": stages,
             "build_s_incl_sync": build_s,
             "layouts_agree": len({r["sum_digest"] for r in res.values()}) == 1}
+
+
+def bench_star(K, dev, stream):
+    """64 star-join queries, fact sizes log-uniform in [1e5, 1e8], product dimension 1e7 rows (Zipf 1.0), customer
+    dimension 2e6 rows (Zipf 0.8), 1-50 % customer filters, SUM(price) by 16 categories; one persistent kernel
+    replayed from a HIP graph, tuning from the autotuner."""
+    import numpy as np
+    import torch
+
+    from paper_1910_10063_amd import skew
+    from paper_1910_10063_amd import workload as W
+
+    k, n_prod, n_cust, nq = 4, 10_000_000, 2_000_000, 64
+    sizes, lt, start = W.star_batch_spec(k, nq, 1e5, 1e8)
+    total = int(start[-1])
+    log(f"star batch: {nq} queries, {total} rows")
+    d = W.device_star_inputs(k, n_prod, n_cust, sizes, device=dev)
+    qs = torch.from_numpy(start).to(dev)
+    ql = torch.from_numpy(lt).to(dev)
+    ident = skew.StarBatch(d["prod"], d["cust"], qs, ql, d["price"], d["category"], d["cust_attr"])
+    bws = skew.workspace(skew.SKEW_OP_BUILD, total, n_prod, dev)
+    t0 = time.time()
+    Lp = skew.build_skew_layout(d["prod"], n_prod, d["price"], d["category"], ws=bws)
+    Lc = skew.build_skew_layout(d["cust"], n_cust, None, d["cust_attr"], ws=bws)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    del bws
+    sk = skew.StarBatch(Lp.fact_recoded, Lc.fact_recoded, qs, ql, Lp.price, Lp.category, Lc.category)
+    ws = skew.star_workspace(sk)
+    out = (torch.empty(nq, 16, dtype=torch.int64, device=dev), torch.empty(nq, 16, dtype=torch.int64, device=dev))
+    t0 = time.time()
+    best, best_ms = skew.star_join_autotune(sk, ws=ws)
+    tune_s = time.time() - t0
+    skew.star_join_batch(sk, best, ws=ws, out=out)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        skew.star_join_batch(sk, best, ws=ws, out=out)
+    torch.cuda.synchronize()
+    ms_graph = timed(g.replay, K, 1, stream)
+    res_s = (out[0].cpu().numpy().copy(), out[1].cpu().numpy().copy())
+    ms_eager = timed(lambda: skew.star_join_batch(sk, best, ws=ws, out=out), K, 1, stream)
+    zero = skew.StarTuning(0, 0, best.tile_rows, 0)
+    ms_ident = timed(lambda: skew.star_join_batch(ident, zero, ws=ws, out=out), K, 1, stream)
+    res_i = (out[0].cpu().numpy().copy(), out[1].cpu().numpy().copy())
+    ibest, ibest_ms = skew.star_join_autotune(ident, ws=ws)
+    ms_ident_tuned = timed(lambda: skew.star_join_batch(ident, ibest, ws=ws, out=out), K, 1, stream)
+    skew.profile_report()
+    skew.profile_enable(True)
+    for _ in range(3):
+        skew.star_join_batch(sk, best, ws=ws, out=out)
+    st = skew.profile_report()
+    skew.profile_enable(False)
+    kern_ms = st["star_batch"][0] / st["star_batch"][1]
+    alg = 8.0 * total + 4.0 * best.prod_hot_rows + 1.0 * best.cust_hot_rows  # two keys per row + hot prefixes
+    res = {"workload": f"batched star join: {nq} queries, {total} fact rows (log-uniform 1e5..1e8), product "
+                       f"{n_prod} rows Zipf(1.0), customer {n_cust} rows Zipf(0.8), 1-50 % customer filters, "
+                       "SUM(price) by 16 categories",
+           "total_rows": total, "graph_ms": ms_graph, "tuples_per_s": total / (ms_graph * 1e-3),
+           "eager_ms": ms_eager, "identity_ms": ms_ident, "identity_autotuned_ms": ms_ident_tuned,
+           "speedup_vs_identity": min(ms_ident, ms_ident_tuned) / ms_graph,
+           "tuning": {"prod_hot_rows": best.prod_hot_rows, "cust_hot_rows": best.cust_hot_rows,
+                      "tile_rows": best.tile_rows, "blocks": best.blocks, "autotune_best_ms": best_ms,
+                      "autotune_s": tune_s},
+           "identity_tuning": {"prod_hot_rows": ibest.prod_hot_rows, "cust_hot_rows": ibest.cust_hot_rows,
+                               "tile_rows": ibest.tile_rows},
+           "kernel_ms": kern_ms, "roofline": {"bound": "hbm", "algorithmic_bytes": alg,
+                                              "achieved_GBps": alg / (kern_ms * 1e-3) / 1e9,
+                                              "frac": alg / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+           "layout_build_s": build_s,
+           "layouts_agree": bool((res_s[0] == res_i[0]).all() and (res_s[1] == res_i[1]).all())}
+    del d, Lp, Lc, sk, ident, ws, g
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_serve(seconds, dev):
+    """Serving loop: Poisson arrivals at 200 requests/s of grouped aggregations over row ranges (log-uniform
+    1e5..5e8 rows) of the resident group-by table (5e8 rows, 1e6 groups, Zipf 1.1); slots from a 16 GB memory
+    budget; at 30 s a new table version with re-permuted popularity arrives (drift, rebuild)."""
+    import torch
+
+    from paper_1910_10063_amd import serving
+    from paper_1910_10063_amd import workload as W
+
+    M, F = 1_000_000, 500_000_000
+    log(f"serving: {seconds} s at 200 requests/s")
+    tabs = []
+    for v, k in ((1, 3), (2, 13)):
+        g = W.device_group_inputs(k, M, F, 1.1, device=dev)
+        tabs.append(serving.TableVersion(v, g["keys"], g["vals"], M))
+    budget = 16 << 30
+    max_rows = F
+    slots = serving.plan_slots(budget, max_rows, M)
+    srv = serving.Server(tabs[0], slots, max_rows)
+    t0 = time.time()
+    serving.start_layout(srv, tabs[0])
+    first_build_s = time.time() - t0
+    arr = serving.poisson_arrivals(200.0, float(seconds), 17)
+    reqs = serving.make_requests(arr, F, 100_000, F, 17)
+    versions = [(30.0, tabs[1])] if seconds > 30 else []
+    done = srv.run(reqs, versions)
+    rep = serving.latency_report(done)
+    rep.update({"workload": f"grouped aggregation requests over row ranges of a {F:.0e}-row, {M:.0e}-group "
+                            "Zipf(1.1) table, Poisson 200/s, ranges log-uniform 1e5..5e8 rows",
+                "seconds": seconds, "slots": slots, "memory_budget_bytes": budget,
+                "slot_bytes": serving.slot_bytes(max_rows, M), "first_layout_build_s": first_build_s,
+                "events": srv.events})
+    del srv, tabs
+    torch.cuda.empty_cache()
+    return rep
 
 
 def bench_cache_model(cbr, rank, N, F, dev):

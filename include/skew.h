@@ -55,6 +55,7 @@ extern "C" {
 #define SKEW_OP_SELECT 7
 #define SKEW_OP_HEAVY 8
 #define SKEW_OP_CACHE_MODEL 9 /* n_keys = keys; sized for lines of 1 value (the largest need) */
+#define SKEW_OP_STAR 10       /* star_join_batch: n_fact = queries, n_keys = max(n_prod, n_cust) */
 
 /* hot_rows / hot_groups special values. */
 #define SKEW_HOT_AUTO (-1)  /* library picks the hot prefix from LDS capacity */
@@ -246,6 +247,63 @@ int heavy_hitter_counts(const int32_t *ranked_keys, int64_t n_fact, int32_t n_ke
 int cache_model_hit_rate(const uint32_t *counts_by_rank, int32_t n_keys, const int32_t *rank,
                          int32_t values_per_line, int64_t cache_lines, double *out_hit, void *workspace,
                          size_t workspace_bytes, void *stream);
+
+/*
+ * Batched star join (the batch workload of the hot-path table): many fact
+ * tables, each with a product key and a customer key per row, joined with a
+ * product dimension (price, category) and a customer dimension (int8
+ * segment).  Query q returns SUM(price) and COUNT(*) grouped by the product's
+ * category (16 groups) over its rows whose customer has segment <
+ * query_cust_lt[q].  It is the FK join-aggregate of Section 1 with a second,
+ * filtering dimension; on frequency-ordered layouts of both dimensions
+ * (Section 3, one layout per dimension built from all queries' keys) the hot
+ * rows of each are the first ones and are read from LDS (Section 4.2).
+ *
+ * One persistent kernel takes tiles of tile_rows rows from a device work queue
+ * (a tile never spans two queries), so queries of very different sizes share
+ * the GPU.  Every launch of the call is a kernel, so a caller may capture the
+ * call in a HIP graph and replay it.
+ */
+typedef struct {
+  int32_t prod_hot_rows; /* product rows [0, t) read from LDS (clamped to capacity) */
+  int32_t cust_hot_rows; /* customer rows [0, t) read from LDS (1 byte each) */
+  int32_t tile_rows;     /* rows per work-queue tile, in [1024, 2^24] */
+  int32_t blocks;        /* persistent workgroups; 0 = one per compute unit */
+} skew_star_tuning;
+
+/*
+ *   prod_keys[N], cust_keys[N]  int32 keys of all queries, one query after the
+ *                               other (N = query_start[n_queries]); both
+ *                               16-byte aligned.
+ *   query_start[n_queries + 1]  int64 device array: query q owns rows
+ *                               [query_start[q], query_start[q + 1]); non-decreasing.
+ *   query_cust_lt[n_queries]    int32 device array: customer threshold of query q.
+ *   n_queries                   1 .. 4096.
+ *   prod_price[n_prod], prod_category[n_prod], cust_segment[n_cust].
+ *   tuning                      host pointer; NULL = defaults (see star_join_autotune).
+ *   out_sum, out_count          int64[n_queries * 16] (query-major).
+ *   workspace                   >= skew_workspace_bytes(SKEW_OP_STAR, n_queries,
+ *                               max(n_prod, n_cust)).
+ * Keys outside their dimension join nothing and set the error flag.
+ */
+int star_join_batch(const int32_t *prod_keys, const int32_t *cust_keys, const int64_t *query_start,
+                    const int32_t *query_cust_lt, int32_t n_queries, const int32_t *prod_price,
+                    const int8_t *prod_category, int32_t n_prod, const int8_t *cust_segment, int32_t n_cust,
+                    const skew_star_tuning *tuning, int64_t *out_sum, int64_t *out_count, void *workspace,
+                    size_t workspace_bytes, void *stream);
+
+/*
+ * star_join_autotune - the autotuner of star_join_batch: runs the batch with
+ * each candidate split of LDS between the two hot prefixes and each tile size,
+ * timing every run with HIP events on `stream`, and writes the fastest tuning
+ * to *best and its time (ms) to *best_ms.  Same arguments as star_join_batch
+ * (the outputs hold the last run's result).  Waits for the stream.
+ */
+int star_join_autotune(const int32_t *prod_keys, const int32_t *cust_keys, const int64_t *query_start,
+                       const int32_t *query_cust_lt, int32_t n_queries, const int32_t *prod_price,
+                       const int8_t *prod_category, int32_t n_prod, const int8_t *cust_segment, int32_t n_cust,
+                       int64_t *out_sum, int64_t *out_count, skew_star_tuning *best, float *best_ms,
+                       void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * skew_query_status - wait for `stream`, then report whether the last query

@@ -107,6 +107,16 @@ hipError_t launch_cache_model(const uint32_t *counts_by_rank, int32_t n_keys, co
                               int32_t values_per_line, int64_t cache_lines, void *ws, double *out_hit,
                               const DeviceInfo &dev, hipStream_t s);
 
+// ---- batched star join ----
+constexpr int32_t kMaxStarQueries = 4096;
+size_t star_lds_bytes(int32_t tp, int32_t tc, int32_t nq);
+int32_t star_max_prod_hot(int32_t tc, int32_t nq, const DeviceInfo &dev);
+size_t star_workspace_bytes(int32_t n_prod, int32_t n_cust, int32_t nq);
+hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t *qstart, const int32_t *qlt,
+                       int32_t nq, const int32_t *price, const int8_t *cat, int32_t n_prod, const int8_t *attr,
+                       int32_t n_cust, int32_t tp, int32_t tc, int64_t tile_rows, int32_t blocks, int64_t *out_sum,
+                       int64_t *out_cnt, int32_t *flag, void *ws, const DeviceInfo &dev, hipStream_t s);
+
 enum GroupMode { kGroupRange = 0, kGroupHash = 1, kGroupAtomic = 2 };
 hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact, int32_t n_groups, GroupMode mode,
                         int32_t hot_groups, const int32_t *perm, int64_t *out_sum, int64_t *out_cnt,

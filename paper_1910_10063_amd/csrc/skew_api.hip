@@ -216,6 +216,8 @@ size_t skew_workspace_bytes(int op, int64_t n_fact, int32_t n_keys) {
       return skew::kFlagBytes;
     case SKEW_OP_CACHE_MODEL:
       return skew::kFlagBytes + round_up(skew::model_workspace_bytes(n_keys, 1));
+    case SKEW_OP_STAR:
+      return skew::kFlagBytes + round_up(skew::star_workspace_bytes(n_keys, n_keys, (int32_t)n_fact));
     case SKEW_OP_SELECT:
       return skew::kFlagBytes + round_up(skew::select_workspace_bytes(n_fact, n_keys, kPartBlocks));
     default:
@@ -466,6 +468,126 @@ int cache_model_hit_rate(const uint32_t *counts_by_rank, int32_t n_keys, const i
                                                 (char *)workspace + skew::kFlagBytes, out_hit, dev,
                                                 (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "cache model");
+  return ok();
+}
+
+namespace {
+
+int star_check(const int32_t *prod_keys, const int32_t *cust_keys, const int64_t *query_start,
+               const int32_t *query_cust_lt, int32_t n_queries, const int32_t *prod_price,
+               const int8_t *prod_category, int32_t n_prod, const int8_t *cust_segment, int32_t n_cust,
+               int64_t *out_sum, int64_t *out_count, void *workspace, size_t workspace_bytes) {
+  if (n_queries < 1 || n_queries > skew::kMaxStarQueries) return fail(SKEW_EINVAL, "n_queries must be in [1, 4096]");
+  if (n_prod < 1 || n_cust < 1) return fail(SKEW_EINVAL, "n_prod and n_cust must be >= 1");
+  if (!prod_keys || !cust_keys || !query_start || !query_cust_lt)
+    return fail(SKEW_EINVAL, "keys and the query table are required");
+  if (!prod_price || !prod_category || !cust_segment) return fail(SKEW_EINVAL, "dimension columns are required");
+  if (!out_sum || !out_count) return fail(SKEW_EINVAL, "outputs are required");
+  if (!workspace) return fail(SKEW_EINVAL, "workspace is NULL");
+  if (((uintptr_t)prod_keys & 15u) || ((uintptr_t)cust_keys & 15u))
+    return fail(SKEW_EINVAL, "key columns must be 16-byte aligned");
+  if (((uintptr_t)query_start & 7u) || ((uintptr_t)out_sum & 7u) || ((uintptr_t)out_count & 7u))
+    return fail(SKEW_EINVAL, "64-bit arrays must be 8-byte aligned");
+  if (!aligned4(query_cust_lt) || !aligned4(prod_price)) return fail(SKEW_EINVAL, "32-bit arrays must be 4-byte aligned");
+  if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = skew::kFlagBytes + round_up(skew::star_workspace_bytes(n_prod, n_cust, n_queries));
+  if (workspace_bytes < need) return fail(SKEW_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  return SKEW_OK;
+}
+
+// Defaults and clamps of a tuning on this device.
+skew_star_tuning star_resolve(const skew_star_tuning *t, int32_t n_prod, int32_t n_cust, int32_t nq,
+                              const skew::DeviceInfo &dev) {
+  skew_star_tuning r;
+  r.cust_hot_rows = t ? t->cust_hot_rows : 16384;
+  r.tile_rows = t ? t->tile_rows : 262144;
+  r.blocks = t && t->blocks > 0 ? t->blocks : dev.cu_count;
+  if (r.cust_hot_rows < 0) r.cust_hot_rows = 0;
+  if (r.cust_hot_rows > n_cust) r.cust_hot_rows = n_cust;
+  const int32_t cmax = 65536 < n_cust ? 65536 : n_cust;  // keep LDS for the product prefix
+  if (r.cust_hot_rows > cmax) r.cust_hot_rows = cmax;
+  const int32_t pmax = skew::star_max_prod_hot(r.cust_hot_rows, nq, dev);
+  r.prod_hot_rows = t && t->prod_hot_rows >= 0 ? t->prod_hot_rows : pmax;
+  if (r.prod_hot_rows > pmax) r.prod_hot_rows = pmax;
+  if (r.prod_hot_rows > n_prod) r.prod_hot_rows = n_prod;
+  if (r.prod_hot_rows < 0) r.prod_hot_rows = 0;
+  if (r.tile_rows < 1024) r.tile_rows = 1024;
+  if (r.tile_rows > (1 << 24)) r.tile_rows = 1 << 24;
+  return r;
+}
+
+}  // namespace
+
+int star_join_batch(const int32_t *prod_keys, const int32_t *cust_keys, const int64_t *query_start,
+                    const int32_t *query_cust_lt, int32_t n_queries, const int32_t *prod_price,
+                    const int8_t *prod_category, int32_t n_prod, const int8_t *cust_segment, int32_t n_cust,
+                    const skew_star_tuning *tuning, int64_t *out_sum, int64_t *out_count, void *workspace,
+                    size_t workspace_bytes, void *stream) {
+  if (int rc = star_check(prod_keys, cust_keys, query_start, query_cust_lt, n_queries, prod_price, prod_category,
+                          n_prod, cust_segment, n_cust, out_sum, out_count, workspace, workspace_bytes))
+    return rc;
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const skew_star_tuning t = star_resolve(tuning, n_prod, n_cust, n_queries, dev);
+  const hipStream_t s = (hipStream_t)stream;
+  const hipError_t e = skew::launch_star(prod_keys, cust_keys, query_start, query_cust_lt, n_queries, prod_price,
+                                         prod_category, n_prod, cust_segment, n_cust, t.prod_hot_rows,
+                                         t.cust_hot_rows, t.tile_rows, t.blocks, out_sum, out_count,
+                                         (int32_t *)workspace, (char *)workspace + skew::kFlagBytes, dev, s);
+  if (e != hipSuccess) return hip_fail(e, "star join launch");
+  if (check_enabled()) return read_flag(workspace, s);
+  return ok();
+}
+
+int star_join_autotune(const int32_t *prod_keys, const int32_t *cust_keys, const int64_t *query_start,
+                       const int32_t *query_cust_lt, int32_t n_queries, const int32_t *prod_price,
+                       const int8_t *prod_category, int32_t n_prod, const int8_t *cust_segment, int32_t n_cust,
+                       int64_t *out_sum, int64_t *out_count, skew_star_tuning *best, float *best_ms,
+                       void *workspace, size_t workspace_bytes, void *stream) {
+  if (int rc = star_check(prod_keys, cust_keys, query_start, query_cust_lt, n_queries, prod_price, prod_category,
+                          n_prod, cust_segment, n_cust, out_sum, out_count, workspace, workspace_bytes))
+    return rc;
+  if (!best || !best_ms) return fail(SKEW_EINVAL, "best and best_ms are required");
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const hipStream_t s = (hipStream_t)stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e != hipSuccess) return hip_fail(e, "autotune events");
+  const int32_t cust_cand[] = {0, 8192, 32768, 65536};
+  const int32_t tile_cand[] = {65536, 262144, 1048576};
+  float best_t = -1.f;
+  skew_star_tuning arg{-1, 0, 0, 0};
+  for (int32_t tc : cust_cand) {
+    for (int32_t tr : tile_cand) {
+      arg.cust_hot_rows = tc;
+      arg.tile_rows = tr;
+      const skew_star_tuning t = star_resolve(&arg, n_prod, n_cust, n_queries, dev);
+      float ms = 0.f;
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // one warm-up, one timed run
+        if (rep == 1) e = hipEventRecord(a, s);
+        if (e == hipSuccess)
+          e = skew::launch_star(prod_keys, cust_keys, query_start, query_cust_lt, n_queries, prod_price,
+                                prod_category, n_prod, cust_segment, n_cust, t.prod_hot_rows, t.cust_hot_rows,
+                                t.tile_rows, t.blocks, out_sum, out_count, (int32_t *)workspace,
+                                (char *)workspace + skew::kFlagBytes, dev, s);
+        if (rep == 1 && e == hipSuccess) e = hipEventRecord(b, s);
+      }
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e != hipSuccess) break;
+      if (best_t < 0.f || ms < best_t) {
+        best_t = ms;
+        *best = t;
+      }
+    }
+    if (e != hipSuccess) break;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return hip_fail(e, "autotune");
+  *best_ms = best_t;
   return ok();
 }
 

@@ -1,0 +1,346 @@
+// Batched star join: many fact tables of uneven sizes, each joined with a
+// product dimension (price summed by category) and a customer dimension that
+// filters (segment < threshold of the query), all in one persistent kernel.
+// Workgroups take tiles of rows from a device work queue; a tile never spans
+// two queries.  Both dimensions keep their hot prefix in LDS (Section 4.2:
+// on the frequency-ordered layouts the hot rows are the first ones) and the
+// rest is gathered through range-checked buffer loads.  Every launch here is
+// a kernel (no memset or host copy), so the whole call can be captured in a
+// HIP graph and replayed.
+#include "kernels.h"
+#include "profiler.h"
+#include "query_common.h"
+
+namespace skew {
+namespace {
+
+constexpr int kStarThreads = 1024;
+constexpr int kStarVecs = 2;       // 16-byte vectors of each key column per lane per batch
+constexpr int kStarBins = kJoinBins;
+
+// Product word: kValid | (category + 1) << 25 | price, kValid alone for a row
+// outside every group, 0 when the price does not fit (slow path).
+__global__ void star_pack_kernel(const int32_t *__restrict__ price, const int8_t *__restrict__ cat, int32_t n_prod,
+                                 uint32_t *__restrict__ words, const int8_t *__restrict__ attr, int32_t n_cust,
+                                 int8_t *__restrict__ attr_copy, int32_t attr_padded) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = gid; r < n_prod; r += stride) {
+    const int32_t p = price[r];
+    const int32_t c = cat[r];
+    uint32_t w = kValid;
+    if (c >= 0 && c < 16) w = ((uint32_t)p <= kPriceMask) ? (kValid | ((uint32_t)(c + 1) << kGroupShift) | (uint32_t)p) : 0u;
+    words[r] = w;
+  }
+  // customer segments, padded to whole words with a value no threshold admits
+  for (int64_t r = gid; r < attr_padded; r += stride) attr_copy[r] = r < n_cust ? attr[r] : (int8_t)127;
+}
+
+// Tile table: tiles of query q start at tile_start[q]; outputs and the queue
+// counter are cleared (one workgroup, n_queries <= kMaxStarQueries).
+__global__ __launch_bounds__(1024) void star_plan_kernel(const int64_t *__restrict__ qstart, int32_t nq,
+                                                         int64_t tile_rows, uint32_t *__restrict__ tile_start,
+                                                         uint32_t *__restrict__ counter, int64_t *__restrict__ out_sum,
+                                                         int64_t *__restrict__ out_cnt, int32_t *flag) {
+  __shared__ uint32_t part[1024];
+  for (int i = threadIdx.x; i < nq * 16; i += blockDim.x) {
+    out_sum[i] = 0;
+    out_cnt[i] = 0;
+  }
+  if (threadIdx.x == 0) {
+    *counter = 0;
+    *flag = 0;
+  }
+  // exclusive scan of the tile counts, kStarQueriesPerThread queries per thread
+  const int per = (nq + 1023) / 1024;
+  const int q0 = threadIdx.x * per;
+  uint32_t sum = 0;
+  for (int q = q0; q < q0 + per && q < nq; ++q) {
+    const int64_t n = qstart[q + 1] - qstart[q];
+    sum += n > 0 ? (uint32_t)((n + tile_rows - 1) / tile_rows) : 0u;
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const uint32_t v = part[i];
+      part[i] = run;
+      run += v;
+    }
+    tile_start[nq] = run;
+  }
+  __syncthreads();
+  uint32_t run = part[threadIdx.x];
+  for (int q = q0; q < q0 + per && q < nq; ++q) {
+    tile_start[q] = run;
+    const int64_t n = qstart[q + 1] - qstart[q];
+    run += n > 0 ? (uint32_t)((n + tile_rows - 1) / tile_rows) : 0u;
+  }
+}
+
+struct StarCtx {
+  const uint32_t *phot;  // LDS: product words [0, tp)
+  uint32_t tp, tpclamp;
+  rsrc_t pwords;         // all product words (range-checked)
+  const uint32_t *chot;  // LDS: customer segments [0, tc) as words
+  uint32_t tc, tcclamp;  // in rows (bytes)
+  rsrc_t cwords;         // all customer segments as words (range-checked)
+  uint32_t n_prod, n_cust;
+};
+
+// Customer segment of row u (0 outside the dimension: checked separately).
+__device__ __forceinline__ int32_t cust_segment(const StarCtx &x, uint32_t u) {
+  const bool hot = u < x.tc;
+  const uint32_t wi = u >> 2;
+  const uint32_t wl = x.chot[wi < x.tcclamp ? wi : x.tcclamp];
+  const uint32_t wg = buffer_load_record(x.cwords, (int32_t)(hot ? 0xFFFFFFFFu : wi), 0, 0, 0);
+  const uint32_t w = hot ? wl : wg;
+  return (int32_t)(int8_t)(w >> (8 * (u & 3u)));
+}
+
+__device__ __forceinline__ uint32_t prod_word(const StarCtx &x, uint32_t p) {
+  const bool hot = p < x.tp;
+  const uint32_t wl = x.phot[p < x.tpclamp ? p : x.tpclamp];
+  const uint32_t wg = buffer_load_record(x.pwords, (int32_t)(hot ? 0xFFFFFFFFu : p), 0, 0, 0);
+  return hot ? wl : wg;
+}
+
+struct StarAcc {
+  uint64_t *bins;  // LDS [kStarBins][64]: count << 44 | sum, bin 0 a sink
+  const int32_t *price;
+  const int8_t *cat;
+  int64_t *out_sum, *out_cnt;  // this query's 16 groups
+  bool bad;
+};
+
+__device__ __forceinline__ void star_add(StarAcc &a, uint32_t w) {
+  const uint32_t bin = (w >> kGroupShift) & (kStarBins - 1);
+  lds_add_u64(&a.bins[bin * kWave + lane_id()], (1ull << kCountShift) | (w & kPriceMask));
+}
+
+// Rare path: a key outside its dimension (joins nothing, sets the flag), or a
+// qualifying product row whose price does not fit the word.
+__device__ __forceinline__ void star_slow(StarAcc &a, const StarCtx &x, uint32_t p, uint32_t u) {
+  if (p >= x.n_prod || u >= x.n_cust) {
+    a.bad = true;
+    return;
+  }
+  const int32_t g = a.cat[p];
+  if (g < 0 || g >= 16) return;
+  global_add_u64(reinterpret_cast<uint64_t *>(&a.out_sum[g]), (uint64_t)(int64_t)a.price[p]);
+  global_add_u64(reinterpret_cast<uint64_t *>(&a.out_cnt[g]), 1ull);
+}
+
+// One row: product word if the customer passes, the sink bin otherwise.
+__device__ __forceinline__ void star_row(StarAcc &a, const StarCtx &x, uint32_t p, uint32_t u, int32_t lt) {
+  const uint32_t wp = prod_word(x, p);
+  const bool pass = u < x.n_cust && cust_segment(x, u) < lt;
+  const uint32_t w = pass ? wp : kValid;
+  star_add(a, w);
+  if (__builtin_expect((pass && wp == 0u) || p >= x.n_prod || u >= x.n_cust, 0)) star_slow(a, x, p, u);
+}
+
+struct KeyPair {
+  i32x4 p, u;
+};
+
+// Flush the bins of the current query: 16 waves, wave g sums bin g + 1.
+__device__ __forceinline__ void star_flush(StarAcc &a) {
+  __syncthreads();
+  const int g = threadIdx.x / kWave;
+  if (g < 16) {
+    uint64_t *b = &a.bins[(g + 1) * kWave + lane_id()];
+    const uint64_t e = *b;
+    *b = 0;
+    const uint64_t s = wave_sum_u64(e & kSumMask);
+    const uint64_t k = wave_sum_u64(e >> kCountShift);
+    if (lane_id() == 0 && k) {
+      global_add_u64(reinterpret_cast<uint64_t *>(&a.out_sum[g]), s);
+      global_add_u64(reinterpret_cast<uint64_t *>(&a.out_cnt[g]), k);
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kStarThreads) void star_batch_kernel(
+    const int32_t *__restrict__ pkeys, const int32_t *__restrict__ ukeys, const int64_t *__restrict__ qstart,
+    const int32_t *__restrict__ qlt, int32_t nq, const uint32_t *__restrict__ tile_start, uint32_t *counter,
+    int64_t tile_rows, const uint32_t *__restrict__ pwords, int32_t n_prod, int32_t tp,
+    const uint32_t *__restrict__ cwords, int32_t n_cust, int32_t tc, const int32_t *__restrict__ price,
+    const int8_t *__restrict__ cat, int64_t *__restrict__ out_sum, int64_t *__restrict__ out_cnt, int32_t *flag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_tile;
+  uint64_t *bins = reinterpret_cast<uint64_t *>(smem);
+  uint32_t *phot = reinterpret_cast<uint32_t *>(smem + kStarBins * kWave * 8);
+  const int32_t tp_words = (tp + 4) & ~3;
+  uint32_t *chot = phot + tp_words;
+  const int32_t tc_words = ((tc + 3) / 4 + 4) & ~3;
+  uint32_t *lts = chot + tc_words;                 // [nq + 1] tile starts
+  for (int i = threadIdx.x; i < kStarBins * kWave; i += blockDim.x) bins[i] = 0;
+  stage_words(phot, pwords, 0, tp);
+  if (tp == 0 && threadIdx.x == 0) phot[0] = 0;
+  stage_words(chot, cwords, 0, (tc + 3) / 4);
+  if (tc == 0 && threadIdx.x == 0) chot[0] = 0;
+  for (int q = threadIdx.x; q <= nq; q += blockDim.x) lts[q] = tile_start[q];
+  __syncthreads();
+
+  StarCtx x;
+  x.phot = phot;
+  x.tp = (uint32_t)tp;
+  x.tpclamp = tp > 0 ? (uint32_t)tp - 1 : 0u;
+  x.pwords = record_buffer(pwords, (uint32_t)n_prod);
+  x.chot = chot;
+  x.tc = (uint32_t)tc;
+  x.tcclamp = tc > 0 ? (uint32_t)((tc + 3) / 4) - 1 : 0u;
+  x.cwords = record_buffer(cwords, (uint32_t)((n_cust + 3) / 4));
+  x.n_prod = (uint32_t)n_prod;
+  x.n_cust = (uint32_t)n_cust;
+  StarAcc a;
+  a.bins = bins;
+  a.price = price;
+  a.cat = cat;
+  a.bad = false;
+  const uint32_t total = lts[nq];
+  const i32x4 *vp = reinterpret_cast<const i32x4 *>(pkeys);
+  const i32x4 *vu = reinterpret_cast<const i32x4 *>(ukeys);
+
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    __syncthreads();  // every thread has read s_tile before it is written again
+    if (tile >= total) break;
+    int32_t lo_q = 0, hi_q = nq - 1;  // last query whose first tile is <= tile
+    while (lo_q < hi_q) {
+      const int32_t m = (lo_q + hi_q + 1) >> 1;
+      if (lts[m] <= tile) lo_q = m;
+      else hi_q = m - 1;
+    }
+    const int32_t q = lo_q;
+    const int64_t r0 = qstart[q] + (int64_t)(tile - lts[q]) * tile_rows;
+    const int64_t r1 = r0 + tile_rows < qstart[q + 1] ? r0 + tile_rows : qstart[q + 1];
+    const int32_t lt = qlt[q];
+    a.out_sum = out_sum + (int64_t)q * 16;
+    a.out_cnt = out_cnt + (int64_t)q * 16;
+    // rows [r0, r1) as item offsets from r0's 16-byte block
+    const int64_t base = r0 & ~(int64_t)3;
+    const i32x4 *bp = vp + base / 4;
+    const i32x4 *bu = vu + base / 4;
+    const int32_t *sp = pkeys + base;
+    const int32_t *su = ukeys + base;
+    walk_items<4, kStarVecs, kStarThreads, KeyPair>(
+        (uint32_t)(r0 - base), (uint32_t)(r1 - base),
+        [&](uint32_t i) { star_row(a, x, (uint32_t)sp[i], (uint32_t)su[i], lt); },
+        [&](uint32_t vi) { return KeyPair{load_stream4(bp + vi), load_stream4(bu + vi)}; },
+        [&](const KeyPair(&kp)[kStarVecs], const bool(&valid)[kStarVecs]) {
+          uint32_t w[4 * kStarVecs], p[4 * kStarVecs], u[4 * kStarVecs];
+          bool pass[4 * kStarVecs];
+#pragma unroll
+          for (int v = 0; v < kStarVecs; ++v) {
+            p[4 * v] = (uint32_t)kp[v].p.x, p[4 * v + 1] = (uint32_t)kp[v].p.y;
+            p[4 * v + 2] = (uint32_t)kp[v].p.z, p[4 * v + 3] = (uint32_t)kp[v].p.w;
+            u[4 * v] = (uint32_t)kp[v].u.x, u[4 * v + 1] = (uint32_t)kp[v].u.y;
+            u[4 * v + 2] = (uint32_t)kp[v].u.z, u[4 * v + 3] = (uint32_t)kp[v].u.w;
+          }
+          uint32_t rare = 0;
+#pragma unroll
+          for (int i = 0; i < 4 * kStarVecs; ++i) {
+            const uint32_t wp = prod_word(x, p[i]);
+            const bool in_c = u[i] < x.n_cust;
+            pass[i] = valid[i / 4] && in_c && cust_segment(x, u[i]) < lt;
+            w[i] = pass[i] ? wp : kValid;
+            rare |= (uint32_t)((pass[i] && wp == 0u) || (valid[i / 4] && (!in_c || p[i] >= x.n_prod)));
+          }
+#pragma unroll
+          for (int i = 0; i < 4 * kStarVecs; ++i) star_add(a, w[i]);
+          if (__builtin_expect(rare != 0u, 0)) {
+#pragma unroll 1
+            for (int i = 0; i < 4 * kStarVecs; ++i) {
+              uint32_t pi = p[0], ui = u[0], wi = w[0];
+              bool ps = pass[0], ok = valid[0];
+#pragma unroll
+              for (int j = 1; j < 4 * kStarVecs; ++j) {
+                pi = i == j ? p[j] : pi;
+                ui = i == j ? u[j] : ui;
+                wi = i == j ? w[j] : wi;
+                ps = i == j ? pass[j] : ps;
+                ok = i == j ? valid[j / 4] : ok;
+              }
+              if ((ps && wi == 0u) || (ok && (ui >= x.n_cust || pi >= x.n_prod))) star_slow(a, x, pi, ui);
+            }
+          }
+        });
+    star_flush(a);
+  }
+  if (a.bad) *flag = 1;
+}
+
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 48 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+}
+
+constexpr size_t kStaticReserve = 512;
+
+}  // namespace
+
+size_t star_lds_bytes(int32_t tp, int32_t tc, int32_t nq) {
+  return (size_t)kStarBins * kWave * 8 + (size_t)((tp + 4) & ~3) * 4 + (size_t)((((tc + 3) / 4) + 4) & ~3) * 4 +
+         (size_t)(nq + 1) * 4;
+}
+
+int32_t star_max_prod_hot(int32_t tc, int32_t nq, const DeviceInfo &dev) {
+  const size_t fixed = star_lds_bytes(0, tc, nq) - 16 + kStaticReserve;
+  if (dev.lds_per_block <= fixed + 16) return 0;
+  return (int32_t)(((dev.lds_per_block - fixed) / 4) & ~(size_t)3) - 4;
+}
+
+size_t star_workspace_bytes(int32_t n_prod, int32_t n_cust, int32_t nq) {
+  auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return r((size_t)n_prod * 4) + r(((size_t)n_cust + 3) / 4 * 4 + 16) + r((size_t)(nq + 1) * 4) + r(16);
+}
+
+hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t *qstart, const int32_t *qlt,
+                       int32_t nq, const int32_t *price, const int8_t *cat, int32_t n_prod, const int8_t *attr,
+                       int32_t n_cust, int32_t tp, int32_t tc, int64_t tile_rows, int32_t blocks, int64_t *out_sum,
+                       int64_t *out_cnt, int32_t *flag, void *ws, const DeviceInfo &dev, hipStream_t s) {
+  auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  char *w = (char *)ws;
+  uint32_t *pwords = (uint32_t *)w;
+  w += r((size_t)n_prod * 4);
+  int8_t *cwords = (int8_t *)w;
+  const int32_t attr_padded = (int32_t)(((int64_t)n_cust + 3) / 4 * 4);
+  w += r((size_t)attr_padded + 16);
+  uint32_t *tile_start = (uint32_t *)w;
+  w += r((size_t)(nq + 1) * 4);
+  uint32_t *counter = (uint32_t *)w;
+
+  StageTimer st = stage_begin("star_prep", s);
+  const int64_t n_pack = n_prod > attr_padded ? n_prod : attr_padded;
+  int64_t g = (n_pack + 255) / 256;
+  if (g > (int64_t)dev.cu_count * 16) g = (int64_t)dev.cu_count * 16;
+  hipLaunchKernelGGL(star_pack_kernel, dim3((int)(g > 0 ? g : 1)), dim3(256), 0, s, price, cat, n_prod, pwords, attr,
+                     n_cust, cwords, attr_padded);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(star_plan_kernel, dim3(1), dim3(1024), 0, s, qstart, nq, tile_rows, tile_start, counter,
+                       out_sum, out_cnt, flag);
+    e = hipGetLastError();
+  }
+  stage_end(st, s);
+  if (e != hipSuccess) return e;
+  const size_t lds = star_lds_bytes(tp, tc, nq);
+  allow_lds(star_batch_kernel, lds);
+  st = stage_begin("star_batch", s);
+  hipLaunchKernelGGL(star_batch_kernel, dim3(blocks), dim3(kStarThreads), lds, s, pkeys, ukeys, qstart, qlt, nq,
+                     tile_start, counter, tile_rows, pwords, n_prod, tp, (const uint32_t *)cwords, n_cust, tc, price,
+                     cat, out_sum, out_cnt, flag);
+  e = hipGetLastError();
+  stage_end(st, s);
+  return e;
+}
+
+}  // namespace skew

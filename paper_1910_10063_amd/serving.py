@@ -1,0 +1,261 @@
+"""Serving loop for grouped aggregation on device-resident tables, with continuous batching.
+
+Requests arrive over time.  Each asks for SUM(value) and COUNT(*) per group over a range of rows of the
+resident fact table (the grouped aggregation Q3 of Section 1).  The server works as follows:
+
+* It keeps the tables on the device.
+* It owns execution slots, as many as a memory budget allows.  Each slot has its own HIP stream, its own
+  workspace and its own output buffers.
+* It admits a waiting request as soon as a slot is free.  Admitted requests run concurrently on their
+  slots' streams, so work from requests that arrived at different times overlaps on the GPU: continuous
+  batching, not a queue in front of one stream.
+* It maintains the frequency-ordered layout (built as in Section 3.1, rebuilt after a batch of updates, as
+  the maintenance discussion there suggests).  A new version of the table, with re-permuted key
+  popularity, is served at once on the identity layout with the library's layout-oblivious method, which
+  gives the same answers.
+* It watches the share of rows that the current layout sends to its hot prefix.  When that share drops
+  (drift), it rebuilds the layout on a side stream and switches to the rebuilt layout when it is ready.
+
+Every step of every request runs in the library's HIP kernels (paper_1910_10063_amd.skew).  This module
+schedules, and it measures latency with wall-clock times at arrival and at completion.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import skew
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float  # seconds since the start of the run
+    start: int      # first row of the range
+    rows: int       # rows in the range
+    version: int = -1       # table version it was answered on
+    layout: str = ""        # "skew" or "identity"
+    admitted: float = math.nan
+    done: float = math.nan
+    digest: tuple[int, int] | None = None
+
+
+@dataclass
+class TableVersion:
+    """One version of the resident fact table and, once built, its frequency-ordered layout."""
+
+    version: int
+    keys: torch.Tensor      # int32 group ids (identity layout)
+    vals: torch.Tensor      # int32 values
+    n_groups: int
+    layout: skew.Layout | None = None
+    hot_share: float = math.nan  # share of rows below the hot threshold on its own layout
+
+
+@dataclass
+class Slot:
+    stream: torch.cuda.Stream
+    ws: torch.Tensor
+    out: tuple[torch.Tensor, torch.Tensor]
+    digest: torch.Tensor
+    done: torch.cuda.Event
+    req: Request | None = None
+
+
+def slot_bytes(max_rows: int, n_groups: int) -> int:
+    """Device bytes one execution slot holds: workspace of the partitioned aggregate plus outputs."""
+    return skew.workspace_bytes(skew.SKEW_OP_GROUP, max_rows, n_groups) + 16 * n_groups + 16
+
+
+def plan_slots(memory_budget: int, max_rows: int, n_groups: int, max_slots: int = 16) -> int:
+    """Number of slots a memory budget admits (at least one)."""
+    return max(1, min(max_slots, memory_budget // slot_bytes(max_rows, n_groups)))
+
+
+def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:
+    """Arrival times of a Poisson process of `rate` per second over [0, duration)."""
+    rng = np.random.default_rng(seed)
+    n = int(rate * duration * 1.5) + 16
+    t = np.cumsum(rng.exponential(1.0 / rate, n))
+    return t[t < duration]
+
+
+def make_requests(arrivals: np.ndarray, table_rows: int, min_rows: int, max_rows: int, seed: int) -> list[Request]:
+    """Row ranges of log-uniform length in [min_rows, max_rows] at uniform positions."""
+    rng = np.random.default_rng(seed + 1)
+    out = []
+    for i, a in enumerate(arrivals):
+        n = int(min_rows * (max_rows / min_rows) ** rng.random())
+        n = min(n, table_rows)
+        s = int(rng.integers(0, table_rows - n + 1))
+        out.append(Request(i, float(a), s, n))
+    return out
+
+
+def start_layout(server: "Server", table: TableVersion) -> None:
+    """Build the first layout synchronously and serve it (before a run)."""
+    server.build_layout(table, torch.cuda.current_stream(server.device))
+    torch.cuda.synchronize(server.device)
+    server.measure_hot_share(table)
+    server.serving_layout = table
+    server.current = table
+
+
+class Server:
+    """Continuous-batching executor of grouped aggregations over a resident, versioned table."""
+
+    def __init__(self, table: TableVersion, n_slots: int, max_rows: int, drift_ratio: float = 0.8,
+                 sample_rows: int = 1 << 22, device="cuda"):
+        self.device = torch.device(device)
+        self.n_groups = table.n_groups
+        self.max_rows = max_rows
+        self.drift_ratio = drift_ratio
+        self.sample_rows = sample_rows
+        self.slots = []
+        for _ in range(n_slots):
+            ws = skew.workspace(skew.SKEW_OP_GROUP, max_rows, self.n_groups, self.device)
+            out = (torch.empty(self.n_groups, dtype=torch.int64, device=self.device),
+                   torch.empty(self.n_groups, dtype=torch.int64, device=self.device))
+            self.slots.append(Slot(torch.cuda.Stream(self.device), ws, out,
+                                   torch.zeros(2, dtype=torch.int64, device=self.device),
+                                   torch.cuda.Event(enable_timing=False)))
+        self.weights = (torch.arange(self.n_groups, device=self.device, dtype=torch.int64) * 2 + 1,
+                        torch.arange(self.n_groups, device=self.device, dtype=torch.int64) + 1)
+        self.side = torch.cuda.Stream(self.device)  # layout rebuilds
+        self.build_ws = None
+        self.current = table
+        self.serving_layout: TableVersion | None = None  # the version whose layout queries use
+        self.rebuild: dict | None = None
+        self.events: list[dict] = []
+        self.t0 = time.perf_counter()
+
+    # ---- time
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    # ---- layout maintenance
+    def build_layout(self, table: TableVersion, stream) -> None:
+        """Frequency-ordered layout of `table` on `stream` (Section 3.1)."""
+        n = table.keys.numel()
+        need = skew.workspace_bytes(skew.SKEW_OP_BUILD, n, self.n_groups)
+        if self.build_ws is None or self.build_ws.numel() < need:
+            self.build_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        with torch.cuda.stream(stream):
+            table.layout = skew.build_skew_layout(table.keys, self.n_groups, ws=self.build_ws)
+
+    def measure_hot_share(self, table: TableVersion) -> None:
+        """Share of the table's rows that its own layout sends to the hot prefix (after its build)."""
+        t = min(skew.max_hot_groups(), self.n_groups)
+        table.hot_share = float(table.layout.counts_by_rank[:t].to(torch.int64).sum().item()) / max(
+            table.keys.numel(), 1)
+
+    def hot_share_under(self, layout_table: TableVersion, table: TableVersion) -> float:
+        """Share of a sample of `table`'s rows whose rank under layout_table's layout is below the hot
+        threshold: selection (Q2) of the rows with rank[key] < t."""
+        t = min(skew.max_hot_groups(), self.n_groups)
+        n = min(self.sample_rows, table.keys.numel())
+        _, cnt = skew.select_fact_rows(table.keys[:n], layout_table.layout.rank, t)
+        return float(cnt.item()) / max(n, 1)
+
+    def install(self, table: TableVersion, rebuild: bool = True) -> None:
+        """A new version of the table arrives: serve it on the identity layout at once; rebuild if drifted."""
+        old = self.serving_layout
+        self.current = table
+        self.events.append({"t": self.now(), "event": "version", "version": table.version})
+        if not rebuild:
+            return
+        drift = True
+        if old is not None and old.layout is not None:
+            share = self.hot_share_under(old, table)
+            drift = share < self.drift_ratio * old.hot_share
+            self.events.append({"t": self.now(), "event": "drift_check", "old_share": old.hot_share,
+                                "new_share": share, "drift": drift})
+        if drift:
+            ev = torch.cuda.Event(enable_timing=True)
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev0.record(self.side)
+            self.build_layout(table, self.side)
+            ev.record(self.side)
+            self.rebuild = {"table": table, "event": ev, "start": ev0, "t": self.now()}
+
+    def poll_rebuild(self) -> None:
+        if self.rebuild is not None and self.rebuild["event"].query():
+            r = self.rebuild
+            self.measure_hot_share(r["table"])
+            self.serving_layout = r["table"]
+            self.events.append({"t": self.now(), "event": "layout_ready", "version": r["table"].version,
+                                "rebuild_ms": r["start"].elapsed_time(r["event"]),
+                                "hot_share": r["table"].hot_share})
+            self.rebuild = None
+
+    # ---- requests
+    def launch(self, slot: Slot, req: Request) -> None:
+        tab = self.current
+        use_skew = self.serving_layout is tab and tab.layout is not None
+        req.version = tab.version
+        req.layout = "skew" if use_skew else "identity"
+        req.admitted = self.now()
+        a, n = req.start, req.rows
+        with torch.cuda.stream(slot.stream):
+            if use_skew:
+                skew.group_aggregate(tab.layout.fact_recoded[a:a + n], tab.vals[a:a + n], self.n_groups,
+                                     hot_groups=skew.SKEW_HOT_AUTO, perm=tab.layout.perm, ws=slot.ws, out=slot.out)
+            else:
+                skew.group_aggregate(tab.keys[a:a + n], tab.vals[a:a + n], self.n_groups, hot_groups=0,
+                                     ws=slot.ws, out=slot.out)
+            # result digest on the device (int64 arithmetic, order-independent)
+            slot.digest[0] = (slot.out[0] * self.weights[0]).sum()
+            slot.digest[1] = (slot.out[1] * self.weights[1]).sum()
+            slot.done.record(slot.stream)
+        slot.req = req
+
+    def harvest(self, slot: Slot) -> Request:
+        req = slot.req
+        d = slot.digest.cpu()  # the slot's stream is complete: done.query() was true
+        req.digest = (int(d[0]), int(d[1]))
+        req.done = self.now()
+        slot.req = None
+        return req
+
+    def run(self, requests: list[Request], versions: list[tuple[float, TableVersion]] | None = None,
+            idle_sleep: float = 0.0) -> list[Request]:
+        """Serve `requests` at their arrival times (seconds from now); install table versions at their times."""
+        versions = sorted(versions or [], key=lambda v: v[0])
+        pending: list[Request] = []
+        finished: list[Request] = []
+        i = vi = 0
+        self.t0 = time.perf_counter()
+        while len(finished) < len(requests):
+            now = self.now()
+            while vi < len(versions) and versions[vi][0] <= now:
+                self.install(versions[vi][1])
+                vi += 1
+            while i < len(requests) and requests[i].arrival <= now:
+                pending.append(requests[i])
+                i += 1
+            self.poll_rebuild()
+            for slot in self.slots:
+                if slot.req is not None and slot.done.query():
+                    finished.append(self.harvest(slot))
+            for slot in self.slots:  # admit in arrival order into every free slot
+                if slot.req is None and pending:
+                    self.launch(slot, pending.pop(0))
+            if idle_sleep and not pending:
+                time.sleep(idle_sleep)
+        torch.cuda.synchronize(self.device)
+        self.poll_rebuild()
+        return finished
+
+
+def latency_report(done: list[Request]) -> dict:
+    lat = np.array([r.done - r.arrival for r in done]) * 1e3
+    rows = sum(r.rows for r in done)
+    span = max(r.done for r in done) - min(r.arrival for r in done)
+    return {"requests": len(done), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "rows": int(rows), "tuples_per_s": rows / span if span > 0 else 0.0,
+            "served_on_skew": sum(r.layout == "skew" for r in done),
+            "served_on_identity": sum(r.layout == "identity" for r in done)}

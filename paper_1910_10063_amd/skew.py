@@ -32,6 +32,7 @@ SKEW_OP_MATERIALIZE = 6
 SKEW_OP_SELECT = 7
 SKEW_OP_HEAVY = 8
 SKEW_OP_CACHE_MODEL = 9
+SKEW_OP_STAR = 10
 
 SKEW_HOT_AUTO = -1
 SKEW_HOT_NONE = -2
@@ -39,7 +40,13 @@ SKEW_HOT_NONE = -2
 EXPORTED = ("skew_last_error", "skew_workspace_bytes", "build_skew_layout", "fk_join_aggregate", "group_aggregate",
             "skew_query_status", "skew_profile_enable", "skew_profile_report", "skew_max_hot_rows",
             "skew_max_hot_groups", "materialize_column", "select_fact_rows", "heavy_hitter_counts", "skew_max_hot",
-            "cache_model_hit_rate")
+            "cache_model_hit_rate", "star_join_batch", "star_join_autotune")
+
+
+class StarTuning(ctypes.Structure):
+    """skew_star_tuning of include/skew.h."""
+    _fields_ = [("prod_hot_rows", ctypes.c_int32), ("cust_hot_rows", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("blocks", ctypes.c_int32)]
 
 
 class SkewError(RuntimeError):
@@ -88,6 +95,10 @@ def load_library(path: str = LIB_PATH):
     lib.heavy_hitter_counts.restype = ctypes.c_int
     lib.cache_model_hit_rate.argtypes = [P, I32, P, I32, I64, P, P, SZ, P]
     lib.cache_model_hit_rate.restype = ctypes.c_int
+    lib.star_join_batch.argtypes = [P, P, P, P, I32, P, P, I32, P, I32, P, P, P, P, SZ, P]
+    lib.star_join_batch.restype = ctypes.c_int
+    lib.star_join_autotune.argtypes = [P, P, P, P, I32, P, P, I32, P, I32, P, P, P, P, P, SZ, P]
+    lib.star_join_autotune.restype = ctypes.c_int
     lib.skew_max_hot.argtypes = [ctypes.c_int]
     lib.skew_max_hot.restype = I64
     if path == LIB_PATH:
@@ -285,6 +296,66 @@ def cache_model_hit_rate(counts_by_rank: torch.Tensor, cache_lines: int, values_
     _check(lib.cache_model_hit_rate(_ptr(counts_by_rank), counts_by_rank.numel(), _ptr(rank), int(values_per_line),
                                     int(cache_lines), ctypes.byref(out), _ptr(ws), ws.numel(), _stream(dev)))
     return out.value
+
+
+@dataclass
+class StarBatch:
+    """Device tensors of one batch: keys of all queries one after the other, the query table, dimensions."""
+
+    prod_keys: torch.Tensor      # int32[N], 16-byte aligned
+    cust_keys: torch.Tensor      # int32[N], 16-byte aligned
+    query_start: torch.Tensor    # int64[n_queries + 1]
+    query_cust_lt: torch.Tensor  # int32[n_queries]
+    price: torch.Tensor          # int32[n_prod]
+    category: torch.Tensor       # int8[n_prod]
+    segment: torch.Tensor        # int8[n_cust]
+
+
+def _star_args(b: StarBatch):
+    for name, t, dt in (("prod_keys", b.prod_keys, torch.int32), ("cust_keys", b.cust_keys, torch.int32),
+                        ("query_start", b.query_start, torch.int64), ("query_cust_lt", b.query_cust_lt, torch.int32),
+                        ("price", b.price, torch.int32), ("category", b.category, torch.int8),
+                        ("segment", b.segment, torch.int8)):
+        _need(t, dt, name)
+    nq = b.query_cust_lt.numel()
+    if b.query_start.numel() != nq + 1:
+        raise ValueError("query_start must have n_queries + 1 entries")
+    return nq, (_ptr(b.prod_keys), _ptr(b.cust_keys), _ptr(b.query_start), _ptr(b.query_cust_lt), nq, _ptr(b.price),
+                _ptr(b.category), b.price.numel(), _ptr(b.segment), b.segment.numel())
+
+
+def star_workspace(b: StarBatch) -> torch.Tensor:
+    return workspace(SKEW_OP_STAR, b.query_cust_lt.numel(), max(b.price.numel(), b.segment.numel()),
+                     b.prod_keys.device)
+
+
+def star_join_batch(b: StarBatch, tuning: StarTuning | None = None, ws: torch.Tensor | None = None,
+                    out: tuple[torch.Tensor, torch.Tensor] | None = None):
+    """(sum, count): int64[n_queries, 16]."""
+    lib = load_library()
+    nq, args = _star_args(b)
+    dev = b.prod_keys.device
+    if out is None:
+        out = (torch.empty(nq, 16, dtype=torch.int64, device=dev), torch.empty(nq, 16, dtype=torch.int64, device=dev))
+    if ws is None:
+        ws = star_workspace(b)
+    _check(lib.star_join_batch(*args, ctypes.byref(tuning) if tuning is not None else None, _ptr(out[0]),
+                               _ptr(out[1]), _ptr(ws), ws.numel(), _stream(dev)))
+    return out
+
+
+def star_join_autotune(b: StarBatch, ws: torch.Tensor | None = None) -> tuple[StarTuning, float]:
+    lib = load_library()
+    nq, args = _star_args(b)
+    dev = b.prod_keys.device
+    out = (torch.empty(nq, 16, dtype=torch.int64, device=dev), torch.empty(nq, 16, dtype=torch.int64, device=dev))
+    if ws is None:
+        ws = star_workspace(b)
+    best = StarTuning()
+    ms = ctypes.c_float(0.0)
+    _check(lib.star_join_autotune(*args, _ptr(out[0]), _ptr(out[1]), ctypes.byref(best), ctypes.byref(ms), _ptr(ws),
+                                  ws.numel(), _stream(dev)))
+    return best, ms.value
 
 
 def max_hot(op: int) -> int:

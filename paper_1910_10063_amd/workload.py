@@ -55,6 +55,10 @@ def value_seed(k: int) -> int:
     return 4000 + k
 
 
+def customer_seed(k: int) -> int:
+    return 3200 + k
+
+
 def splitmix64(z: np.ndarray) -> np.ndarray:
     """SplitMix64 output function applied elementwise to a uint64 array."""
     z = np.asarray(z, dtype=np.uint64)
@@ -227,3 +231,51 @@ def device_group_inputs(k: int, n_groups: int, n_fact: int, s: float, vmax: int 
     del cdf_d
     vals = device_uniform_i32(value_seed(k), 0, vmax, n_fact, device)
     return dict(keys=keys, vals=vals, pi=pi, cdf=cdf)
+
+
+# ---------------------------------------------------------------------------
+# Batched star-join workload: a product dimension (price, category), a
+# customer dimension (segment U[0, 99] int8), and a batch of fact tables of
+# log-uniform sizes, each with a product key (Zipf s_prod through pi_p) and a
+# customer key (Zipf s_cust through pi_c), stored one after the other.
+# ---------------------------------------------------------------------------
+def star_batch_spec(k: int, n_queries: int, fmin: float, fmax: float):
+    """Row counts floor(fmin * (fmax / fmin) ** u) and customer thresholds U[1, 50] (1-50 % selectivity)."""
+    u = unit_double(stream(5000 + k, 0, n_queries))
+    sizes = np.floor(fmin * (fmax / fmin) ** u).astype(np.int64)
+    lt = uniform_int(5100 + k, 1, 50, n_queries).astype(np.int32)
+    start = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return sizes, lt, start
+
+
+def star_dimensions(k: int, n_prod: int, n_cust: int):
+    price, cat = dimension(k, n_prod)
+    attr = uniform_int(customer_seed(k), 0, 99, n_cust).astype(np.int8)
+    return price, cat, attr
+
+
+def host_star_inputs(k: int, n_prod: int, n_cust: int, sizes, s_prod: float = 1.0, s_cust: float = 0.8):
+    total = int(np.sum(sizes))
+    pi_p = permutation(perm_seed(k), n_prod)
+    pi_c = permutation(2100 + k, n_cust)
+    prod = fact_keys(fact_seed(k), zipf_cdf(n_prod, s_prod), pi_p, total)
+    cust = fact_keys(1100 + k, zipf_cdf(n_cust, s_cust), pi_c, total)
+    price, cat, attr = star_dimensions(k, n_prod, n_cust)
+    return dict(prod=prod, cust=cust, price=price, category=cat, cust_attr=attr)
+
+
+def device_star_inputs(k: int, n_prod: int, n_cust: int, sizes, s_prod: float = 1.0, s_cust: float = 0.8,
+                       device="cuda"):
+    import torch
+
+    total = int(np.sum(sizes))
+    pi_p = torch.from_numpy(permutation(perm_seed(k), n_prod)).to(device)
+    pi_c = torch.from_numpy(permutation(2100 + k, n_cust)).to(device)
+    cdf = torch.from_numpy(zipf_cdf(n_prod, s_prod)).to(device)
+    prod = device_fact_keys(fact_seed(k), cdf, pi_p, total)
+    cdf = torch.from_numpy(zipf_cdf(n_cust, s_cust)).to(device)
+    cust = device_fact_keys(1100 + k, cdf, pi_c, total)
+    del cdf
+    price, cat, attr = star_dimensions(k, n_prod, n_cust)
+    return dict(prod=prod, cust=cust, price=torch.from_numpy(price).to(device),
+                category=torch.from_numpy(cat).to(device), cust_attr=torch.from_numpy(attr).to(device))

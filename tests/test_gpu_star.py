@@ -1,0 +1,135 @@
+"""GPU parity of the batched star join against the CPU oracle, bit-exact.
+
+A batch of fact tables of uneven sizes (empty, ragged, several tiles) with a
+product key and a customer key per row; every query's SUM(price) and
+COUNT(*) by category over rows whose customer segment passes its threshold
+must equal the oracle's, on the identity layouts and on the frequency-ordered
+layouts of both dimensions (built from all queries' keys), for many tunings,
+and from a HIP graph replayed several times.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1910_10063_amd import skew
+from paper_1910_10063_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+SIZES = np.array([0, 1, 3, 5, 1000, 4097, 65537, 0, 300_000, 1_000_003, 2], dtype=np.int64)
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def batch():
+    k, n_prod, n_cust = 4, 20_000, 5_000
+    say(f"star batch n_prod={n_prod} n_cust={n_cust} sizes={SIZES.tolist()}")
+    h = W.host_star_inputs(k, n_prod, n_cust, SIZES)
+    lt = np.array([1, 50, 25, 7, 33, 50, 12, 40, 2, 49, 30], dtype=np.int32)
+    start = np.concatenate([[0], np.cumsum(SIZES)]).astype(np.int64)
+    want = []
+    for q in range(SIZES.size):
+        a, b = start[q], start[q + 1]
+        want.append(oracle.star_join(h["prod"][a:b], h["cust"][a:b], h["price"], h["category"], h["cust_attr"], lt[q]))
+    ident = skew.StarBatch(to_dev(h["prod"]), to_dev(h["cust"]), to_dev(start), to_dev(lt), to_dev(h["price"]),
+                           to_dev(h["category"]), to_dev(h["cust_attr"]))
+    Lp = skew.build_skew_layout(ident.prod_keys, n_prod, ident.price, ident.category)
+    Lc = skew.build_skew_layout(ident.cust_keys, n_cust, None, ident.segment)
+    sk = skew.StarBatch(Lp.fact_recoded, Lc.fact_recoded, ident.query_start, ident.query_cust_lt, Lp.price,
+                        Lp.category, Lc.category)
+    return dict(identity=ident, skew=sk, want=want)
+
+
+def check(out, want):
+    s, c = host(out[0]), host(out[1])
+    for q, (ws, wc) in enumerate(want):
+        assert (s[q] == ws).all() and (c[q] == wc).all(), q
+
+
+@pytest.mark.parametrize("tun", [None, (0, 0, 1024, 0), (0, 0, 65536, 1), (37, 100, 4096, 7),
+                                 (-1, 5000, 1 << 20, 0), (-1, 0, 3000, 3), (20_000, 4999, 262_144, 0)],
+                         ids=str)
+@pytest.mark.parametrize("layout", ["skew", "identity"])
+def test_star_batch(batch, tun, layout):
+    say(f"star batch {layout} tuning={tun}")
+    t = None if tun is None else skew.StarTuning(*tun)
+    check(skew.star_join_batch(batch[layout], t), batch["want"])
+
+
+def test_star_autotune(batch):
+    say("star autotune")
+    best, ms = skew.star_join_autotune(batch["skew"])
+    assert ms > 0 and best.tile_rows >= 1024
+    check(skew.star_join_batch(batch["skew"], best), batch["want"])
+
+
+def test_star_graph_replay(batch):
+    """The call captured in a HIP graph: every replay equals the eager result."""
+    say("star graph capture and replay")
+    b = batch["skew"]
+    ws = skew.star_workspace(b)
+    nq = b.query_cust_lt.numel()
+    out = (torch.empty(nq, 16, dtype=torch.int64, device=DEV), torch.empty(nq, 16, dtype=torch.int64, device=DEV))
+    tun = skew.StarTuning(-1, 4096, 65536, 0)
+    skew.star_join_batch(b, tun, ws=ws, out=out)  # eager run (also sets the kernel's LDS limit)
+    torch.cuda.synchronize()
+    check(out, batch["want"])
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        skew.star_join_batch(b, tun, ws=ws, out=out)
+    for i in range(4):
+        out[0].fill_(-1)
+        out[1].fill_(-7)
+        junk = torch.randn(1 << 20, device=DEV).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        check(out, batch["want"])
+        assert torch.isfinite(junk)
+
+
+def test_star_out_of_range_keys(batch):
+    say("star out-of-range keys")
+    b = batch["identity"]
+    p = b.prod_keys.clone()
+    u = b.cust_keys.clone()
+    p[10] = 20_000
+    u[1500] = -1
+    bad = skew.StarBatch(p, u, b.query_start, b.query_cust_lt, b.price, b.category, b.segment)
+    ws = skew.star_workspace(bad)
+    skew.star_join_batch(bad, ws=ws)
+    with pytest.raises(skew.SkewError):
+        skew.query_status(ws)
+
+
+def test_star_rejects_unaligned_keys(batch):
+    b = batch["identity"]
+    lib = skew.load_library()
+    ws = skew.star_workspace(b)
+    out = torch.empty(2, b.query_cust_lt.numel(), 16, dtype=torch.int64, device=DEV)
+    rc = lib.star_join_batch(ctypes.c_void_p(b.prod_keys.data_ptr() + 4), ctypes.c_void_p(b.cust_keys.data_ptr()),
+                             ctypes.c_void_p(b.query_start.data_ptr()), ctypes.c_void_p(b.query_cust_lt.data_ptr()),
+                             b.query_cust_lt.numel(), ctypes.c_void_p(b.price.data_ptr()),
+                             ctypes.c_void_p(b.category.data_ptr()), b.price.numel(),
+                             ctypes.c_void_p(b.segment.data_ptr()), b.segment.numel(), None,
+                             ctypes.c_void_p(out[0].data_ptr()), ctypes.c_void_p(out[1].data_ptr()),
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), None)
+    assert rc == skew.SKEW_EINVAL
