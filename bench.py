@@ -299,6 +299,8 @@ def main():
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(C, price, cat, args.cpu_rows, skew_res if args.cpu_rows >= F else None)
+        if not args.no_extras:
+            result["cpu_baseline"]["other_rows"] = cpu_baseline_rows()
         if "bit_exact_vs_oracle" in result["cpu_baseline"]:
             result["bit_exact_vs_oracle"] = result["cpu_baseline"].pop("bit_exact_vs_oracle")
     print(json.dumps(result), flush=True)
@@ -558,6 +560,52 @@ def cpu_baseline(C, price, cat, rows, gpu_res):
            "cpu_model": _cpu_model()}
     if gpu_res is not None:
         out["bit_exact_vs_oracle"] = bool((s == gpu_res[0]).all() and (c == gpu_res[1]).all())
+    return out
+
+
+def cpu_baseline_rows(n=20_000_000):
+    """The oracle timed on bounded samples of every other row's workload (one thread each): the first n
+    rows of the same seeded columns the device sections use (the generators are counter-based)."""
+    import numpy as np
+
+    import oracle
+    from paper_1910_10063_amd import workload as W
+
+    out = {}
+
+    def timed_cpu(name, fn, rows, sample):
+        t = time.perf_counter()
+        fn()
+        dt = time.perf_counter() - t
+        out[name] = {"value": rows / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+                     "sample": f"{sample}; {dt:.2f} s on 1 thread"}
+
+    log(f"cpu oracle samples of {n} rows")
+    h = W.host_join_inputs(2, 10_000_000, n, 1.0)
+    timed_cpu("build_layout", lambda: oracle.build_layout(h["fact"], 10_000_000, h["price"], h["category"]), n,
+              f"first {n} keys of the 1e9-key join column, N = 1e7")
+    timed_cpu("materialize", lambda: oracle.materialize(h["fact"], h["price"]), n, f"first {n} keys of the join column")
+    timed_cpu("select", lambda: oracle.select(h["fact"], h["price"], 100), n, f"first {n} keys, price < 100")
+    timed_cpu("heavy_hitters", lambda: oracle.heavy_hitters(h["fact"], 10_000_000, 4000), n,
+              f"first {n} keys, k = 4000 (count every key, then sort)")
+    del h
+    g = W.host_group_inputs(3, 1_000_000, n, 1.1)
+    timed_cpu("group_by", lambda: oracle.group_aggregate(g["keys"], g["vals"], 1_000_000), n,
+              f"first {n} rows of the 5e8-row group-by table")
+    del g
+    sizes, lt, start = W.star_batch_spec(4, 64, 1e5, 1e8)
+    m = min(n, int(start[-1]))
+    st = W.host_star_inputs(4, 10_000_000, 2_000_000, np.array([m]))  # rows [0, m) of the batch columns
+    cuts = [int(x) for x in start if x < m] + [m]
+
+    def star():
+        for i in range(len(cuts) - 1):  # each piece of [0, m) with the threshold of its query
+            a, b = cuts[i], cuts[i + 1]
+            if b > a:
+                oracle.star_join(st["prod"][a:b], st["cust"][a:b], st["price"], st["category"], st["cust_attr"],
+                                 int(lt[i]))
+
+    timed_cpu("star_batch", star, m, f"the first {m} rows of the batch, each with its query's threshold")
     return out
 
 
