@@ -28,8 +28,8 @@ hipError_t launch_rank_sort(const uint32_t *counts_by_key, int32_t n_keys, int64
 hipError_t launch_inverse(const int32_t *perm, int32_t n, int32_t *rank, hipStream_t s);
 hipError_t launch_permute_dims(const int32_t *perm, int32_t n, const int32_t *price, const int8_t *cat,
                                int32_t *price_out, int8_t *cat_out, hipStream_t s);
-hipError_t launch_recode(const int32_t *keys, int64_t n, const int32_t *rank, int32_t n_keys, int32_t *out,
-                         const DeviceInfo &dev, hipStream_t s);
+hipError_t launch_recode(const int32_t *keys, int64_t n, const int32_t *rank, const int32_t *perm, int32_t n_keys,
+                         int32_t *out, const DeviceInfo &dev, hipStream_t s);
 
 // ---- prefix sums and cold-item partitioning ----
 struct SliceTables;

@@ -2,6 +2,7 @@
 // dimension copy and fact recoding (Section 3.1 and Section 3.2).
 #include "device_common.h"
 #include "kernels.h"
+#include "query_common.h"
 
 namespace skew {
 namespace {
@@ -272,6 +273,120 @@ __global__ __launch_bounds__(kRecodeThreads) void recode_kernel(const int32_t *k
   }
 }
 
+// ---------------------------------------------------------------------------
+// Recode with the hot keys in LDS.  Once the ranks are known, the hottest
+// keys are known too (perm[0..T)): every workgroup inserts them, hottest
+// first, into an LDS hash table of 4-slot buckets (key -> rank; a key whose
+// bucket is full stays out), and each fact key is looked up there with one
+// 16-byte LDS read before falling back to the rank array in global memory.
+// ---------------------------------------------------------------------------
+constexpr int kRecodeHotThreads = 1024;
+constexpr int kRecodeBucketBits = 12;
+constexpr int kRecodeBuckets = 1 << kRecodeBucketBits;  // 4096 buckets x 4 slots, keys + ranks = 128 KB
+constexpr int kRecodeHotVecs = 4;
+
+__device__ __forceinline__ uint32_t recode_bucket(uint32_t k) { return (k * 0x9E3779B1u) >> (32 - kRecodeBucketBits); }
+
+__device__ __forceinline__ int32_t recode_hot_one(const int32_t *tkeys, const int32_t *tranks, rsrc_t ranks,
+                                                  uint32_t n_keys, int32_t k) {
+  const uint32_t uk = (uint32_t)k;
+  const uint32_t b = recode_bucket(uk) * 4;
+  const i32x4 ks = *reinterpret_cast<const i32x4 *>(tkeys + b);
+  const i32x4 rs = *reinterpret_cast<const i32x4 *>(tranks + b);
+  const bool h0 = ks.x == k, h1 = ks.y == k, h2 = ks.z == k, h3 = ks.w == k;
+  const bool hit = h0 || h1 || h2 || h3;
+  const int32_t rl = h0 ? rs.x : (h1 ? rs.y : (h2 ? rs.z : rs.w));
+  const int32_t rg = (int32_t)buffer_load_record(ranks, (int32_t)(hit ? 0xFFFFFFFFu : uk), 0, 0, 0);
+  return uk < n_keys ? (hit ? rl : rg) : k;
+}
+
+__global__ __launch_bounds__(kRecodeHotThreads) void recode_hot_kernel(const int32_t *keys, int64_t n,
+                                                                       const int32_t *__restrict__ rank,
+                                                                       const int32_t *__restrict__ perm,
+                                                                       int32_t n_keys, int32_t n_hot, int32_t *out) {
+  __shared__ __align__(16) int32_t tkeys[kRecodeBuckets * 4];
+  __shared__ __align__(16) int32_t tranks[kRecodeBuckets * 4];
+  for (int i = threadIdx.x; i < kRecodeBuckets * 4; i += blockDim.x) tkeys[i] = -1;
+  __syncthreads();
+  for (int32_t r0 = 0; r0 < n_hot; r0 += kRecodeHotThreads) {  // hottest ranks claim slots first
+    const int32_t r = r0 + (int32_t)threadIdx.x;
+    if (r < n_hot) {
+      const int32_t k = perm[r];
+      const uint32_t b = recode_bucket((uint32_t)k) * 4;
+      for (int j = 0; j < 4; ++j) {
+        if (atomicCAS(&tkeys[b + j], -1, k) == -1) {
+          tranks[b + j] = r;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const rsrc_t rk = record_buffer(rank, (uint32_t)n_keys);
+  const uint32_t nk = (uint32_t)n_keys;
+  // keys may alias out (in-place recode): each element is read and then written by one thread, and a
+  // tile is loaded before the previous one is written, never after.
+  const Split4 sp = split4(keys, n);
+  if ((((uintptr_t)keys ^ (uintptr_t)out) & 15u) != 0) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
+      out[j] = recode_hot_one(tkeys, tranks, rk, nk, keys[j]);
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < sp.head) out[threadIdx.x] = recode_hot_one(tkeys, tranks, rk, nk, keys[threadIdx.x]);
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x >= kWave && threadIdx.x - kWave < n - sp.tail) {
+    const int64_t j = sp.tail + threadIdx.x - kWave;
+    out[j] = recode_hot_one(tkeys, tranks, rk, nk, keys[j]);
+  }
+  const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
+  i32x4 *vo = reinterpret_cast<i32x4 *>(out + sp.head);
+  const int64_t per = (sp.nvec + gridDim.x - 1) / gridDim.x;
+  const int64_t vb = (int64_t)blockIdx.x * per < sp.nvec ? (int64_t)blockIdx.x * per : sp.nvec;
+  const int64_t ve = vb + per < sp.nvec ? vb + per : sp.nvec;
+  constexpr int64_t kTile = (int64_t)kRecodeHotThreads * kRecodeHotVecs;
+  const int64_t full_end = vb + ((ve - vb) / kTile) * kTile;
+  auto resolve = [&](const i32x4(&x)[kRecodeHotVecs], int64_t base, bool guard) {
+#pragma unroll
+    for (int u = 0; u < kRecodeHotVecs; ++u) {
+      const int64_t vi = base + u * kRecodeHotThreads + threadIdx.x;
+      if (guard && vi >= ve) continue;
+      i32x4 y;
+      y.x = recode_hot_one(tkeys, tranks, rk, nk, x[u].x);
+      y.y = recode_hot_one(tkeys, tranks, rk, nk, x[u].y);
+      y.z = recode_hot_one(tkeys, tranks, rk, nk, x[u].z);
+      y.w = recode_hot_one(tkeys, tranks, rk, nk, x[u].w);
+      store_stream4(vo + vi, y);
+    }
+  };
+  auto load_tile = [&](i32x4(&x)[kRecodeHotVecs], int64_t base) {
+#pragma unroll
+    for (int u = 0; u < kRecodeHotVecs; ++u) x[u] = load_stream4(vk + base + u * kRecodeHotThreads + threadIdx.x);
+  };
+  i32x4 xa[kRecodeHotVecs], xb[kRecodeHotVecs];
+  int64_t base = vb;
+  if (base < full_end) load_tile(xa, base);
+  while (base < full_end) {
+    int64_t nxt = base + kTile;
+    load_tile(xb, nxt < full_end ? nxt : base);
+    resolve(xa, base, false);
+    base = nxt;
+    if (base >= full_end) break;
+    nxt = base + kTile;
+    load_tile(xa, nxt < full_end ? nxt : base);
+    resolve(xb, base, false);
+    base = nxt;
+  }
+  if (full_end < ve) {
+    i32x4 x[kRecodeHotVecs];
+#pragma unroll
+    for (int u = 0; u < kRecodeHotVecs; ++u) {
+      const int64_t vi = full_end + u * kRecodeHotThreads + threadIdx.x;
+      x[u] = vi < ve ? load_stream4(vk + vi) : i32x4{0, 0, 0, 0};
+    }
+    resolve(x, full_end, true);
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -352,9 +467,15 @@ hipError_t launch_permute_dims(const int32_t *perm, int32_t n, const int32_t *pr
   return hipGetLastError();
 }
 
-hipError_t launch_recode(const int32_t *keys, int64_t n, const int32_t *rank, int32_t n_keys, int32_t *out,
-                         const DeviceInfo &dev, hipStream_t s) {
+hipError_t launch_recode(const int32_t *keys, int64_t n, const int32_t *rank, const int32_t *perm, int32_t n_keys,
+                         int32_t *out, const DeviceInfo &dev, hipStream_t s) {
   if (n <= 0) return hipSuccess;
+  if (perm && n >= (int64_t)dev.cu_count * 65536) {  // large columns: hot keys through LDS
+    const int32_t n_hot = n_keys < 3 * kRecodeBuckets ? n_keys : 3 * kRecodeBuckets;  // 75 % of the slots
+    hipLaunchKernelGGL(recode_hot_kernel, dim3(dev.cu_count), dim3(kRecodeHotThreads), 0, s, keys, n, rank, perm,
+                       n_keys, n_hot, out);
+    return hipGetLastError();
+  }
   const int64_t need = (n + 4LL * kRecodeThreads - 1) / (4LL * kRecodeThreads);
   int grid = dev.cu_count * 8;
   if (need < grid) grid = (int)need;

@@ -286,7 +286,7 @@ int build_skew_layout(const int32_t *fact_keys, int64_t n_fact, int32_t n_keys, 
   if (e == hipSuccess) e = skew::launch_permute_dims(perm, n_keys, dim_price, dim_category, price_out, category_out, s);
   skew::stage_end(st, s);
   st = skew::stage_begin("build_recode", s);
-  if (e == hipSuccess && fact_recoded) e = skew::launch_recode(fact_keys, n_fact, rank, n_keys, fact_recoded, dev, s);
+  if (e == hipSuccess && fact_recoded) e = skew::launch_recode(fact_keys, n_fact, rank, perm, n_keys, fact_recoded, dev, s);
   skew::stage_end(st, s);
   if (e != hipSuccess) return hip_fail(e, "layout launch");
   return ok();

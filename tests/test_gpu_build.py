@@ -104,3 +104,17 @@ def test_partitioned_build_three_rounds():
     check(L, ref)
     del d, L
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("N,s,in_place,offset", [(100, 1.0, False, 0), (2_000_000, 1.0, True, 0),
+                                                 (10_000_000, 0.0, False, 1), (50_000, 1.5, True, 3)])
+def test_recode_hot_keys(N, s, in_place, offset):
+    """Columns of at least 2^24 keys recode through an LDS table of the hottest keys."""
+    F = (1 << 24) + 4099
+    say(f"recode hot keys N={N} s={s} in_place={in_place} offset={offset}")
+    h = W.host_join_inputs(8, N, F + offset, s)
+    fact = h["fact"][offset:]
+    ref = oracle.build_layout(fact, N)
+    buf = to_dev(h["fact"])
+    L = skew.build_skew_layout(buf[offset:], N, in_place=in_place)
+    check(L, ref)
