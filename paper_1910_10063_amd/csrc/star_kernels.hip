@@ -99,10 +99,13 @@ __device__ __forceinline__ int32_t cust_segment(const StarCtx &x, uint32_t u) {
   return (int32_t)(int8_t)(w >> (8 * (u & 3u)));
 }
 
-__device__ __forceinline__ uint32_t prod_word(const StarCtx &x, uint32_t p) {
+// Product word of row p for a row whose customer passed; for the other rows
+// the gather index is pushed out of range, so a filtered row costs no memory
+// traffic (their word is never used).
+__device__ __forceinline__ uint32_t prod_word(const StarCtx &x, uint32_t p, bool pass) {
   const bool hot = p < x.tp;
   const uint32_t wl = x.phot[p < x.tpclamp ? p : x.tpclamp];
-  const uint32_t wg = buffer_load_record(x.pwords, (int32_t)(hot ? 0xFFFFFFFFu : p), 0, 0, 0);
+  const uint32_t wg = buffer_load_record(x.pwords, (int32_t)(hot || !pass ? 0xFFFFFFFFu : p), 0, 0, 0);
   return hot ? wl : wg;
 }
 
@@ -134,8 +137,8 @@ __device__ __forceinline__ void star_slow(StarAcc &a, const StarCtx &x, uint32_t
 
 // One row: product word if the customer passes, the sink bin otherwise.
 __device__ __forceinline__ void star_row(StarAcc &a, const StarCtx &x, uint32_t p, uint32_t u, int32_t lt) {
-  const uint32_t wp = prod_word(x, p);
   const bool pass = u < x.n_cust && cust_segment(x, u) < lt;
+  const uint32_t wp = prod_word(x, p, pass);
   const uint32_t w = pass ? wp : kValid;
   star_add(a, w);
   if (__builtin_expect((pass && wp == 0u) || p >= x.n_prod || u >= x.n_cust, 0)) star_slow(a, x, p, u);
@@ -246,9 +249,9 @@ __global__ __launch_bounds__(kStarThreads) void star_batch_kernel(
           uint32_t rare = 0;
 #pragma unroll
           for (int i = 0; i < 4 * kStarVecs; ++i) {
-            const uint32_t wp = prod_word(x, p[i]);
             const bool in_c = u[i] < x.n_cust;
             pass[i] = valid[i / 4] && in_c && cust_segment(x, u[i]) < lt;
+            const uint32_t wp = prod_word(x, p[i], pass[i]);
             w[i] = pass[i] ? wp : kValid;
             rare |= (uint32_t)((pass[i] && wp == 0u) || (valid[i / 4] && (!in_c || p[i] >= x.n_prod)));
           }
