@@ -313,7 +313,7 @@ int star_join_autotune(const int32_t *prod_keys, const int32_t *cust_keys, const
 int skew_query_status(const void *workspace, size_t workspace_bytes, void *stream);
 
 /* Stage timing, for benchmarks.  While enabled (on != 0), every launch stage
- * of the calls above (e.g. "join_split", "join_partition", "join_slice",
+ * of the calls above (e.g. "join_pack", "join_split", "join_scatter", "join_slice",
  * "build_histogram") records a pair of HIP events on the stream it runs on.
  * skew_profile_report waits for them, writes up to max_stages entries (stage
  * names as consecutive NUL-terminated strings in names[names_bytes], total
