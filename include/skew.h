@@ -145,7 +145,9 @@ int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *d
  *                       bins (clamped to capacity); the rest are either
  *                       partitioned into slices of 8192 groups and summed in
  *                       LDS (workspace of SKEW_OP_GROUP size) or sent to global
- *                       atomics (single-pass workspace).  0: no id-based
+ *                       atomics (single-pass workspace).  In the partitioned
+ *                       form a bin takes rows with values in [0, 2^16); a hot
+ *                       row with another value is partitioned like a cold one.  0: no id-based
  *                       privatisation, the layout-oblivious method: every row
  *                       partitioned (large workspace) or an LDS hash table of
  *                       the first groups met (single pass).  SKEW_HOT_NONE:
@@ -323,7 +325,9 @@ void skew_profile_enable(int on);
 int skew_profile_report(char *names, int names_bytes, float *ms, int *calls, int max_stages);
 
 /* Hot-prefix capacities (rows / groups) the kernels can hold in LDS on the
- * current device, or a negative code. */
+ * current device, or a negative code.  skew_max_hot_groups is the capacity
+ * of the partitioned group-by (8 bytes per group; it may hold a few more when
+ * there are fewer slices); the single pass holds fewer (12 bytes per group). */
 int32_t skew_max_hot_rows(int32_t group_by_category);
 int32_t skew_max_hot_groups(void);
 /* op: SKEW_OP_MATERIALIZE (rows), SKEW_OP_SELECT (rows, i.e. bits), SKEW_OP_HEAVY

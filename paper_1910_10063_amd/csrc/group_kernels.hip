@@ -37,6 +37,7 @@ struct GroupCtx {
   // [kCopySlots + g]; one array keeps every update a single LDS atomic.
   uint64_t *hot_sum;
   uint32_t *hot_cnt;
+  uint64_t *pack;      // pass 1 of the partitioned form: packed bins, same slot order
   int32_t *slot_key;   // hash mode [kHashSlots]
   uint64_t *slot_sum;
   uint32_t *slot_cnt;
@@ -206,28 +207,71 @@ __global__ __launch_bounds__(kGroupThreads) void group_kernel(const int32_t *__r
 }
 
 // ---------------------------------------------------------------------------
-// Partitioned form, pass 1: hot groups into LDS bins; every other valid
-// (group, value) pair appended to this workgroup's segment of the cold
-// buffer and counted in its slice ((g - t) >> wshift).
+// Partitioned form, pass 1: rows of hot groups into LDS bins; every other
+// valid (group, value) pair appended to this workgroup's segment of the cold
+// buffer and counted in its slice (g >> wshift; slices cover all groups, so
+// that a hot row the bins cannot take is resolved like a cold one).
+//
+// A bin is one 64-bit word, count << 40 | sum, updated by a single LDS atomic.
+// It takes rows whose value lies in [0, 2^16); it stays exact while it sees
+// fewer than 2^24 rows, since the sum then stays below 2^40, and the plan
+// gives every workgroup fewer than 2^24 rows per launch.  Rows of hot groups
+// with other values go to the cold buffer.
 // ---------------------------------------------------------------------------
 constexpr int kSplitVecs = 2;  // 16-byte vectors of keys (and of values) per lane per batch
+constexpr int kPackShift = 40;
+constexpr uint64_t kPackSumMask = (1ull << kPackShift) - 1ull;
+constexpr uint32_t kPackValueLimit = 1u << 16;
+constexpr int64_t kPackMaxRows = 1LL << 24;  // rows a workgroup may give one launch of pass 1
 
-// Hot update without branches: lanes whose group is not hot add into a sink
-// slot of their own (kCopySlots + t + lane).
-__device__ __forceinline__ void group_hot_or_sink(const GroupCtx &c, bool h, uint32_t g, int32_t v, uint32_t sink) {
-  const uint32_t i = h ? (g < (uint32_t)c.ncopy ? g * kWave + lane_id() : kCopySlots + g) : sink;
-  lds_add_u64(&c.hot_sum[i], (uint64_t)(int64_t)v);
-  lds_add_u32(&c.hot_cnt[i], 1u);
+// LDS layout of pass 1: pack[kCopySlots + t + kWave] (per-lane copies, bins,
+// one sink slot per lane that is never flushed).
+__device__ __forceinline__ void group_pack_init(GroupCtx &c, unsigned char *smem) {
+  c.pack = reinterpret_cast<uint64_t *>(smem);
+  for (int i = threadIdx.x; i < kCopySlots + c.t + kWave; i += blockDim.x) c.pack[i] = 0;
 }
 
-struct PairSeg {
-  rsrc_t keys, vals;  // this workgroup's segment
+// Hot update without branches: lanes whose row is not taken add into a sink
+// slot of their own (kCopySlots + t + lane).
+__device__ __forceinline__ void group_pack_or_sink(const GroupCtx &c, bool h, uint32_t g, int32_t v, uint32_t sink) {
+  const uint32_t i = h ? (g < (uint32_t)c.ncopy ? g * kWave + lane_id() : kCopySlots + g) : sink;
+  lds_add_u64(&c.pack[i], (1ull << kPackShift) | (uint32_t)v);
+}
+
+__device__ __forceinline__ void group_pack_flush(const GroupCtx &c) {
+  const int w = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  for (int g = w; g < c.ncopy; g += nw) {
+    const uint64_t x = c.pack[g * kWave + lane_id()];
+    const uint64_t s = wave_sum_u64(x & kPackSumMask);
+    const uint64_t k = wave_sum_u64(x >> kPackShift);
+    if (lane_id() == 0 && k) {
+      global_add_u64(&c.acc_sum[g], s);
+      global_add_u64(&c.acc_cnt[g], k);
+    }
+  }
+  for (int g = c.ncopy + threadIdx.x; g < c.t; g += blockDim.x) {
+    const uint64_t x = c.pack[kCopySlots + g];
+    if (x) {
+      global_add_u64(&c.acc_sum[g], x & kPackSumMask);
+      global_add_u64(&c.acc_cnt[g], x >> kPackShift);
+    }
+  }
+}
+
+struct PairSeg {  // this workgroup's segment; stores a chunk of (group, value) pairs
+  rsrc_t keys, vals;
+  __device__ __forceinline__ void operator()(const uint32_t (&col)[2], int32_t idx, bool ok) const {
+    const int32_t i = ok ? idx : -1;  // -1: out of range, dropped
+    buffer_store_record((int32_t)col[0], keys, i, 0, 0, 0);
+    buffer_store_record((int32_t)col[1], vals, i, 0, 0, 0);
+  }
 };
 
 template <int V>
-__device__ __forceinline__ void group_split_batch(GroupCtx &c, const ColdSink &o, const PairSeg &seg,
-                                                  uint32_t hot_sink, const i32x4 (&x)[V], const i32x4 (&y)[V],
-                                                  const bool (&valid)[V]) {
+__device__ __forceinline__ void group_split_batch(GroupCtx &c, const ColdSink &o, WaveChunk<2> &ch,
+                                                  const PairSeg &seg, uint32_t hot_sink, const i32x4 (&x)[V],
+                                                  const i32x4 (&y)[V], const bool (&valid)[V]) {
   uint32_t g[4 * V];
   int32_t v[4 * V];
   bool cold[4 * V];
@@ -242,28 +286,29 @@ __device__ __forceinline__ void group_split_batch(GroupCtx &c, const ColdSink &o
     const bool ok = valid[i / 4];
     const bool in = ok && g[i] < (uint32_t)c.m;
     c.bad |= ok && !in;
-    const bool h = in && g[i] < (uint32_t)c.t;
+    const bool h = in && g[i] < (uint32_t)c.t && (uint32_t)v[i] < kPackValueLimit;
     cold[i] = in && !h;
-    group_hot_or_sink(c, h, g[i], v[i], hot_sink);
+    group_pack_or_sink(c, h, g[i], v[i], hot_sink);
   }
-  cold_append(o, g, cold, [&](int i, int32_t idx) {
-    buffer_store_record((int32_t)g[i], seg.keys, idx, 0, 0, 0);
-    buffer_store_record(v[i], seg.vals, idx, 0, 0, 0);
-  });
+  uint32_t cols[4 * V][2];
+#pragma unroll
+  for (int i = 0; i < 4 * V; ++i) {
+    cols[i][0] = g[i];
+    cols[i][1] = (uint32_t)v[i];
+  }
+  cold_append_dense(o, ch, g, cold, cols, seg);
 }
 
-__device__ __forceinline__ void group_split_one(GroupCtx &c, const ColdSink &o, const PairSeg &seg, uint32_t hot_sink,
-                                                bool valid, int32_t gi, int32_t v) {
+__device__ __forceinline__ void group_split_one(GroupCtx &c, const ColdSink &o, WaveChunk<2> &ch, const PairSeg &seg,
+                                                uint32_t hot_sink, bool valid, int32_t gi, int32_t v) {
   const uint32_t g[1] = {(uint32_t)gi};
   const bool in = valid && g[0] < (uint32_t)c.m;
   c.bad |= valid && !in;
-  const bool h = in && g[0] < (uint32_t)c.t;
+  const bool h = in && g[0] < (uint32_t)c.t && (uint32_t)v < kPackValueLimit;
   const bool cold[1] = {in && !h};
-  group_hot_or_sink(c, h, g[0], v, hot_sink);
-  cold_append(o, g, cold, [&](int, int32_t idx) {
-    buffer_store_record(gi, seg.keys, idx, 0, 0, 0);
-    buffer_store_record(v, seg.vals, idx, 0, 0, 0);
-  });
+  group_pack_or_sink(c, h, g[0], v, hot_sink);
+  const uint32_t cols[1][2] = {{(uint32_t)gi, (uint32_t)v}};
+  cold_append_dense(o, ch, g, cold, cols, seg);
 }
 
 __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
@@ -279,8 +324,8 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
   c.acc_sum = acc_sum;
   c.acc_cnt = acc_cnt;
   c.bad = false;
-  group_range_init(c, smem, t, kWave);
-  uint32_t *lhist = c.hot_cnt + kCopySlots + t + kWave;
+  group_pack_init(c, smem);
+  uint32_t *lhist = reinterpret_cast<uint32_t *>(c.pack + kCopySlots + t + kWave);
   uint32_t *lcount = lhist + P + kWave;
   for (int p = threadIdx.x; p < P + kWave; p += blockDim.x) lhist[p] = 0;
   if (threadIdx.x == 0) *lcount = 0;
@@ -288,13 +333,16 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
   ColdSink o;
   o.count = lcount;
   o.hist = lhist;
-  o.t = (uint32_t)t;
+  o.t = 0;  // slices of all groups
   o.wshift = wshift;
   o.sink = (uint32_t)P + lane_id();
   PairSeg seg;
   seg.keys = record_buffer(seg_keys + (int64_t)blockIdx.x * seg_cap, (uint32_t)seg_cap);
   seg.vals = record_buffer(seg_vals + (int64_t)blockIdx.x * seg_cap, (uint32_t)seg_cap);
   const uint32_t hot_sink = (uint32_t)(kCopySlots + t) + lane_id();
+  WaveChunk<2> ch;
+  ch.n = 0;
+  ch.col[0] = ch.col[1] = 0;
 
   // Workgroup b owns rows [b * per, (b + 1) * per) (in 4-row vectors when the
   // two columns are aligned together, else in single rows).
@@ -306,7 +354,7 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
       if (blockIdx.x == 0 && threadIdx.x < sp.head) i = threadIdx.x;
       if (blockIdx.x == gridDim.x - 1 && threadIdx.x >= 64 && threadIdx.x - 64 < n - sp.tail)
         i = sp.tail + threadIdx.x - 64;
-      group_split_one(c, o, seg, hot_sink, i >= 0, i >= 0 ? keys[i] : 0, i >= 0 ? vals[i] : 0);
+      group_split_one(c, o, ch, seg, hot_sink, i >= 0, i >= 0 ? keys[i] : 0, i >= 0 ? vals[i] : 0);
     }
     const int64_t per = (sp.nvec + gridDim.x - 1) / gridDim.x;
     const int64_t vb = (int64_t)blockIdx.x * per < sp.nvec ? (int64_t)blockIdx.x * per : sp.nvec;
@@ -331,12 +379,12 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
     while (base < full_end) {  // the next tile is loaded while the current one is processed
       int64_t nxt = base + tile_vecs;
       load_tile(xb, yb, nxt < full_end ? nxt : base);
-      group_split_batch<kSplitVecs>(c, o, seg, hot_sink, xa, ya, all_valid);
+      group_split_batch<kSplitVecs>(c, o, ch, seg, hot_sink, xa, ya, all_valid);
       base = nxt;
       if (base >= full_end) break;
       nxt = base + tile_vecs;
       load_tile(xa, ya, nxt < full_end ? nxt : base);
-      group_split_batch<kSplitVecs>(c, o, seg, hot_sink, xb, yb, all_valid);
+      group_split_batch<kSplitVecs>(c, o, ch, seg, hot_sink, xb, yb, all_valid);
       base = nxt;
     }
     if (full_end < ve) {  // last partial tile
@@ -349,7 +397,7 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
         x[u] = valid[u] ? load_stream4(vk + vi) : i32x4{0, 0, 0, 0};
         y[u] = valid[u] ? load_stream4(vv + vi) : i32x4{0, 0, 0, 0};
       }
-      group_split_batch<kSplitVecs>(c, o, seg, hot_sink, x, y, valid);
+      group_split_batch<kSplitVecs>(c, o, ch, seg, hot_sink, x, y, valid);
     }
   } else {
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
@@ -358,15 +406,16 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
     for (int64_t base = rb; base < re; base += blockDim.x) {
       const int64_t i = base + threadIdx.x;
       const bool valid = i < re;
-      group_split_one(c, o, seg, hot_sink, valid, valid ? load_stream1(keys + i) : 0,
+      group_split_one(c, o, ch, seg, hot_sink, valid, valid ? load_stream1(keys + i) : 0,
                       valid ? load_stream1(vals + i) : 0);
     }
   }
+  chunk_drain(o, ch, seg);
   if (c.bad) *flag = 1;
   __syncthreads();
   if (threadIdx.x == 0) seg_count[blockIdx.x] = *lcount < seg_cap ? *lcount : (uint32_t)seg_cap;
   for (int p = threadIdx.x; p < P; p += blockDim.x) hist[(int64_t)p * gridDim.x + blockIdx.x] = lhist[p];
-  group_range_flush(c);
+  group_pack_flush(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -484,19 +533,30 @@ size_t group_lds_bytes(int32_t hot_groups) {
 }
 
 int32_t group_max_hot_groups(const DeviceInfo &dev) {
-  // + sink slots and slice histogram of pass 1
-  const size_t fixed = group_lds_bytes(0) + (size_t)kWave * 12 + (size_t)(kMaxSlices + kWave + 4) * 4;
+  const size_t fixed = group_lds_bytes(0);
   if (dev.lds_per_block <= fixed) return 0;
   return (int32_t)((dev.lds_per_block - fixed) / 12);
 }
 
-GroupPlan group_plan(int64_t n_fact, int32_t n_groups, int32_t t, const DeviceInfo &dev) {
+size_t group_split_lds_bytes(int32_t hot_groups, int32_t slices) {
+  // packed bins (copies, groups, sinks), then the slice histogram with its sinks and item count
+  return (size_t)(kCopySlots + (hot_groups > 0 ? hot_groups : 0) + kWave) * 8 + (size_t)(slices + kWave + 4) * 4;
+}
+
+int32_t group_split_max_hot_groups(int32_t slices, const DeviceInfo &dev) {
+  const size_t fixed = group_split_lds_bytes(0, slices);
+  if (dev.lds_per_block <= fixed) return 0;
+  return (int32_t)((dev.lds_per_block - fixed) / 8);
+}
+
+GroupPlan group_plan(int64_t n_fact, int32_t n_groups, const DeviceInfo &dev) {
   GroupPlan pl;
-  pl.blocks = dev.cu_count > 0 ? dev.cu_count : 256;
+  // at least 32 workgroups: every workgroup gets fewer than kPackMaxRows rows of a round
+  pl.blocks = dev.cu_count > 32 ? dev.cu_count : 32;
   pl.wshift = kGroupSliceShift;
-  const int64_t cold = (int64_t)n_groups - t;
-  pl.slices = cold > 0 ? (int32_t)((cold + (1 << pl.wshift) - 1) >> pl.wshift) : 0;
+  pl.slices = (int32_t)(((int64_t)n_groups + (1 << pl.wshift) - 1) >> pl.wshift);
   pl.round = n_fact < kMaxRound ? n_fact : kMaxRound;
+  static_assert(kMaxRound / 32 + 64 < kPackMaxRows, "pass-1 bins must see fewer than 2^24 rows");
   // rows per workgroup (vector ranges round up by at most 4 rows per block,
   // plus the scalar head and tail), with a generous margin
   pl.seg_cap = 4 * (((pl.round + pl.blocks - 1) / pl.blocks + 64 + 3) / 4);
@@ -527,18 +587,19 @@ hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact
   stage_end(st, s);
   if (e != hipSuccess) return e;
   if (n_fact > 0) {
+    const GroupPlan pl = group_plan(n_fact, n_groups, dev);
+    const bool partitioned = mode != kGroupAtomic && part_ws && n_fact >= kPartitionMinFact && pl.slices > 0 &&
+                             pl.slices <= kMaxSlices && part_bytes >= group_partition_bytes(pl);
+    // t is clamped to the LDS capacity of the form that runs
     int32_t t = hot_groups;
     if (mode == kGroupRange) {
-      const int32_t cap = group_max_hot_groups(dev);
+      const int32_t cap = partitioned ? group_split_max_hot_groups(pl.slices, dev) : group_max_hot_groups(dev);
       if (t > cap) t = cap;
       if (t > n_groups) t = n_groups;
       if (t < 0) t = 0;
     } else {
       t = 0;
     }
-    const GroupPlan pl = group_plan(n_fact, n_groups, t, dev);
-    const bool partitioned = mode != kGroupAtomic && part_ws && n_fact >= kPartitionMinFact && pl.slices > 0 &&
-                             pl.slices <= kMaxSlices && part_bytes >= group_partition_bytes(pl);
     if (!partitioned) {
       const size_t lds =
           mode == kGroupRange ? group_lds_bytes(t) : (mode == kGroupHash ? (size_t)kHashSlots * 16 : 0);
@@ -585,7 +646,7 @@ hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact
       tab.seg_count = (uint32_t *)ws;
       ws += r((size_t)pl.blocks * 4);
       tab.slice_off = (uint32_t *)ws;
-      const size_t lds1 = group_lds_bytes(t) + (size_t)kWave * 12 + (size_t)(pl.slices + kWave + 4) * 4;
+      const size_t lds1 = group_split_lds_bytes(t, pl.slices);
       const size_t lds3 = ((size_t)12 << pl.wshift) + (size_t)(pl.slices + 1) * 4;
       allow_lds(group_split_kernel, lds1);
       allow_lds(group_slice_kernel, lds3);
@@ -602,13 +663,13 @@ hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact
         stage_end(st, s);
         st = stage_begin("group_scatter", s);
         if (e == hipSuccess)
-          e = launch_partition_scatter(tab, pl.slices, pl.blocks, seg_k, seg_v, pl.seg_cap, t, pl.wshift, items_k,
+          e = launch_partition_scatter(tab, pl.slices, pl.blocks, seg_k, seg_v, pl.seg_cap, 0, pl.wshift, items_k,
                                        items_v, s);
         stage_end(st, s);
         if (e != hipSuccess) return e;
         st = stage_begin("group_slice", s);
         hipLaunchKernelGGL(group_slice_kernel, dim3(pl.blocks), dim3(kGroupThreads), lds3, s, items_k, items_v,
-                           tab.slice_off, pl.slices, n_groups, t, pl.wshift, acc_sum, acc_cnt);
+                           tab.slice_off, pl.slices, n_groups, 0, pl.wshift, acc_sum, acc_cnt);
         e = hipGetLastError();
         stage_end(st, s);
         if (e != hipSuccess) return e;

@@ -78,8 +78,10 @@ int32_t join_max_hot_rows(int groups, const DeviceInfo &dev);
 JoinPlan join_plan(int64_t n_fact, int32_t n_rows, int32_t t, int groups, const DeviceInfo &dev);
 size_t join_partition_bytes(const JoinPlan &pl);
 size_t group_lds_bytes(int32_t hot_groups);
-int32_t group_max_hot_groups(const DeviceInfo &dev);
-GroupPlan group_plan(int64_t n_fact, int32_t n_groups, int32_t t, const DeviceInfo &dev);
+int32_t group_max_hot_groups(const DeviceInfo &dev);  // single pass
+size_t group_split_lds_bytes(int32_t hot_groups, int32_t slices);
+int32_t group_split_max_hot_groups(int32_t slices, const DeviceInfo &dev);  // partitioned form
+GroupPlan group_plan(int64_t n_fact, int32_t n_groups, const DeviceInfo &dev);
 size_t group_partition_bytes(const GroupPlan &pl);
 
 // part_ws/part_bytes: optional workspace for the partitioned form (NULL: single pass).

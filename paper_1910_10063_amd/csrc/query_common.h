@@ -135,6 +135,75 @@ __device__ __forceinline__ void cold_append(const ColdSink &o, const uint32_t (&
 }
 
 // ---------------------------------------------------------------------------
+// Dense form of the compaction, for a low cold share: the cold slots of a
+// wave are moved by one lane permutation per slot into an open chunk of 64
+// items held in registers (lane L holds item L of the chunk, NC columns); a
+// full chunk takes one reservation and one dense store per column, so every
+// store carries 64 items whatever the share of cold slots.  Items reach the
+// segment in no particular order; the partition needs none.  Every lane of
+// the wave must be active.
+// ---------------------------------------------------------------------------
+template <int NC>
+struct WaveChunk {
+  uint32_t col[NC];
+  uint32_t n;  // items held, wave-uniform
+};
+
+// store(col, idx, ok): lanes with ok write their items at segment index idx.
+template <int NC, class Store>
+__device__ __forceinline__ void chunk_append(const ColdSink &o, WaveChunk<NC> &ch, bool cold,
+                                             const uint32_t (&x)[NC], Store store) {
+  const uint64_t m = __ballot(cold);
+  const uint32_t n = (uint32_t)__popcll(m);
+  if (n == 0) return;
+  const uint32_t lane = lane_id();
+  const uint32_t below = lanes_below(m);
+  // cold lanes first, in lane order, then the others: a permutation of the
+  // 64 lanes, rotated so that the cold items follow the open chunk
+  const uint32_t rank = cold ? below : n + (lane - below);
+  const int addr = (int)(((ch.n + rank) & (kWave - 1)) << 2);
+  uint32_t y[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) y[j] = (uint32_t)__builtin_amdgcn_ds_permute(addr, (int)x[j]);
+  const uint32_t end = ch.n + n;
+  const bool take = lane >= ch.n && lane < end;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) ch.col[j] = take ? y[j] : ch.col[j];
+  if (end >= (uint32_t)kWave) {
+    const uint32_t pos = wave_reserve(o.count, kWave);
+    store(ch.col, (int32_t)(pos + lane), true);
+    const bool wrap = lane < end - kWave;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) ch.col[j] = wrap ? y[j] : ch.col[j];
+    ch.n = end - kWave;
+  } else {
+    ch.n = end;
+  }
+}
+
+// The items left in the open chunk at the end of the workgroup's range.
+template <int NC, class Store>
+__device__ __forceinline__ void chunk_drain(const ColdSink &o, WaveChunk<NC> &ch, Store store) {
+  if (ch.n == 0) return;
+  const uint32_t pos = wave_reserve(o.count, ch.n);
+  store(ch.col, (int32_t)(pos + lane_id()), lane_id() < ch.n);
+  ch.n = 0;
+}
+
+// Slots k[i] with cold[i] go to the open chunk and are counted in their
+// slice; the other lanes count into their sink word.
+template <int N, int NC, class Store>
+__device__ __forceinline__ void cold_append_dense(const ColdSink &o, WaveChunk<NC> &ch, const uint32_t (&k)[N],
+                                                  const bool (&cold)[N], const uint32_t (&cols)[N][NC],
+                                                  Store store) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    chunk_append(o, ch, cold[i], cols[i], store);
+    lds_add_u32(&o.hist[cold[i] ? (k[i] - o.t) >> o.wshift : o.sink], 1u);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Items [lo, hi) of item arrays that hold IPV items per 16-byte vector (and
 // start 16-byte aligned at item 0), visited by a workgroup of THREADS
 // threads: the items before the first vector boundary (threads 0..) and after

@@ -136,7 +136,7 @@ size_t group_ws(int32_t n_groups) { return skew::kFlagBytes + 2 * round_up((size
 
 size_t group_part_ws(int64_t n_fact, int32_t n_groups) {
   if (n_fact < skew::kPartitionMinFact) return 0;
-  const skew::GroupPlan pl = skew::group_plan(n_fact, n_groups, 0, sizing_device());
+  const skew::GroupPlan pl = skew::group_plan(n_fact, n_groups, sizing_device());
   if (pl.slices <= 0 || pl.slices > skew::kMaxSlices) return 0;
   return round_up(skew::group_partition_bytes(pl));
 }
@@ -356,7 +356,7 @@ int group_aggregate(const int32_t *group_keys, const int32_t *values, int64_t n_
     mode = skew::kGroupHash;
     if (dev.lds_per_block < 128 * 1024) return fail(SKEW_EDEVICE, "hash privatisation needs 128 KB of LDS");
   } else if (hot_groups == SKEW_HOT_AUTO) {
-    t = skew::group_max_hot_groups(dev);
+    t = INT32_MAX;  // clamped to the LDS capacity of the form that runs
   }
   const hipStream_t s = (hipStream_t)stream;
   char *ws = (char *)workspace;
@@ -649,7 +649,7 @@ int32_t skew_max_hot_rows(int32_t group_by_category) {
 int32_t skew_max_hot_groups(void) {
   skew::DeviceInfo dev;
   if (int rc = device_info(&dev)) return rc;
-  return skew::group_max_hot_groups(dev);
+  return skew::group_split_max_hot_groups(skew::kMaxSlices, dev);
 }
 
 int64_t skew_max_hot(int op) {

@@ -336,6 +336,28 @@ def test_negative_values_and_large_counts():
         assert (host(s) == es).all() and (host(c) == ec).all(), t
 
 
+@pytest.mark.parametrize("offset", [0, 2])
+def test_partitioned_group_value_boundaries(offset):
+    """Pass 1 of the partitioned group-by packs count and sum of a hot group into one word for values in
+    [0, 2^16); values at and around that boundary, on hot and cold groups, with one very hot group."""
+    say(f"group value boundaries offset={offset}")
+    rng = np.random.default_rng(70 + offset)
+    M, F = 40_000, (1 << 22) + 77
+    keys = (rng.zipf(1.1, F + offset) % M).astype(np.int32)
+    keys[rng.random(F + offset) < 0.3] = 0  # one group takes a third of the rows
+    edge = np.array([0, 1, 65534, 65535, 65536, 65537, -1, -65536, 2**31 - 1, -2**31], np.int64)
+    vals = edge[rng.integers(0, edge.size, F + offset)].astype(np.int32)
+    vals[rng.random(F + offset) < 0.5] = 65535
+    es, ec, inv = oracle.group_aggregate(keys[offset:], vals[offset:], M)
+    assert inv == 0
+    kd, vd = to_dev(keys)[offset:], to_dev(vals)[offset:]
+    ws = skew.workspace(skew.SKEW_OP_GROUP, F, M, DEV)
+    for t in (1, 16, 17, 3000, M, skew.SKEW_HOT_AUTO):
+        s, c = skew.group_aggregate(kd, vd, M, hot_groups=t, ws=ws)
+        assert (host(s) == es).all() and (host(c) == ec).all(), t
+    assert skew.query_status(ws) == skew.SKEW_OK
+
+
 def test_generator_device_matches_host():
     say("generator: device vs host")
     for n_ranks, s in ((100_000, 1.0), (1_000_000, 1.1), (1000, 0.0)):
