@@ -163,6 +163,10 @@ def main():
     log("skew-layout query (timed steps)")
     ms_skew = timed(query(Cp, pp, cp, t_hot), K, WU, stream)
     skew_res = (out_s.cpu().numpy().copy(), out_c.cpu().numpy().copy())
+    # achievable read rate of this device: one read pass over the 4 GB column with 16-byte loads
+    log("stream probe (read bandwidth)")
+    ms_probe = timed(lambda: skew.stream_probe(Cp), K, 1, stream)
+    probe_gbs = 4.0 * F / (ms_probe * 1e-3) / 1e9
     ms_ident, agree = None, None
     if not args.skew_only:
         log("identity-layout query")
@@ -220,7 +224,8 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": dom_bytes, "kernel_ms": round(dom_ms, 4),
-                "launches_per_query": launches, "cold_fact_keys": cold}
+                "launches_per_query": launches, "cold_fact_keys": cold,
+                "frac_of_read_probe": round(achieved / probe_gbs, 4)}
     q_bytes = 4.0 * F + 9.0 * N  # whole query: every fact key once, both dimension columns once
     query_roofline = {"bound": "hbm", "algorithmic_bytes": q_bytes,
                       "achieved": round(q_bytes / (ms_skew * 1e-3) / 1e9, 1),
@@ -247,6 +252,8 @@ def main():
                              "category": W.category_seed(k)}},
         "roofline": roofline,
         "query_roofline": query_roofline,
+        "read_probe": {"kernel": "stream_probe", "bytes": 4.0 * F, "ms": round(ms_probe, 4),
+                       "GB_per_s": round(probe_gbs, 1), "frac_of_peak": round(probe_gbs / HBM_PEAK_GBS, 4)},
         "identity": {"value": F / (ms_ident * 1e-3), "ms_per_step": ms_ident} if ms_ident else None,
         "speedup_vs_identity": ms_ident / ms_skew if ms_ident else None,
         "stages_ms": {"skew": stages_skew, "identity": stages_ident, "build": per_query(st_build, 1)},

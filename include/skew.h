@@ -314,6 +314,22 @@ int star_join_autotune(const int32_t *prod_keys, const int32_t *cust_keys, const
  */
 int skew_query_status(const void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * stream_probe - measurement: one read pass over `bytes` of device memory
+ * with 16-byte loads; *out_sum receives the 64-bit wrapping sum of its 32-bit
+ * words (so no load can be skipped).  Timed by the caller, it gives the HBM
+ * read rate a streaming kernel reaches on the device, the practical ceiling
+ * beside the published peak for the query passes, which mostly read.
+ *
+ *   buf       device pointer, 16-byte aligned (NULL allowed when bytes = 0).
+ *   bytes     multiple of 16.
+ *   out_sum   device pointer to one uint64, overwritten.
+ *
+ * Stream-ordered.  SKEW_EINVAL for a NULL or misaligned pointer or a size
+ * that is not a multiple of 16.
+ */
+int stream_probe(const void *buf, size_t bytes, uint64_t *out_sum, void *stream);
+
 /* Stage timing, for benchmarks.  While enabled (on != 0), every launch stage
  * of the calls above (e.g. "join_pack", "join_split", "join_scatter", "join_slice",
  * "build_histogram") records a pair of HIP events on the stream it runs on.

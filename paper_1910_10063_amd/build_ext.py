@@ -34,7 +34,8 @@ FLAGS = [
 
 TARGETS = {
     "libskew.so": ["skew_api.hip", "layout_kernels.hip", "partition_kernels.hip", "join_kernels.hip",
-                   "group_kernels.hip", "operator_kernels.hip", "model_kernels.hip", "star_kernels.hip"],
+                   "group_kernels.hip", "operator_kernels.hip", "model_kernels.hip", "star_kernels.hip",
+                   "probe_kernels.hip"],
     "libskewgen.so": ["workload_gen.hip"],
 }
 

@@ -119,6 +119,12 @@ hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t
                        int32_t n_cust, int32_t tp, int32_t tc, int64_t tile_rows, int32_t blocks, int64_t *out_sum,
                        int64_t *out_cnt, int32_t *flag, void *ws, const DeviceInfo &dev, hipStream_t s);
 
+// ---- measurement ----
+// One read pass over bytes (a multiple of 16) of a 16-byte aligned buffer;
+// *out_sum (device) receives the 64-bit wrapping sum of its 32-bit words.
+hipError_t launch_stream_probe(const void *buf, size_t bytes, uint64_t *out_sum, const DeviceInfo &dev,
+                               hipStream_t s);
+
 enum GroupMode { kGroupRange = 0, kGroupHash = 1, kGroupAtomic = 2 };
 hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact, int32_t n_groups, GroupMode mode,
                         int32_t hot_groups, const int32_t *perm, int64_t *out_sum, int64_t *out_cnt,

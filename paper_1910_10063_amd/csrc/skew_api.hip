@@ -450,6 +450,18 @@ int heavy_hitter_counts(const int32_t *ranked_keys, int64_t n_fact, int32_t n_ke
   return ok();
 }
 
+int stream_probe(const void *buf, size_t bytes, uint64_t *out_sum, void *stream) {
+  if (!out_sum) return fail(SKEW_EINVAL, "out_sum is NULL");
+  if (bytes > 0 && !buf) return fail(SKEW_EINVAL, "buf is NULL");
+  if (((uintptr_t)buf & 15u) || (bytes & 15u)) return fail(SKEW_EINVAL, "buf and bytes must be 16-byte multiples");
+  if ((uintptr_t)out_sum & 7u) return fail(SKEW_EINVAL, "out_sum must be 8-byte aligned");
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const hipError_t e = skew::launch_stream_probe(buf, bytes, out_sum, dev, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream probe");
+  return ok();
+}
+
 int cache_model_hit_rate(const uint32_t *counts_by_rank, int32_t n_keys, const int32_t *rank,
                          int32_t values_per_line, int64_t cache_lines, double *out_hit, void *workspace,
                          size_t workspace_bytes, void *stream) {

@@ -40,7 +40,7 @@ SKEW_HOT_NONE = -2
 EXPORTED = ("skew_last_error", "skew_workspace_bytes", "build_skew_layout", "fk_join_aggregate", "group_aggregate",
             "skew_query_status", "skew_profile_enable", "skew_profile_report", "skew_max_hot_rows",
             "skew_max_hot_groups", "materialize_column", "select_fact_rows", "heavy_hitter_counts", "skew_max_hot",
-            "cache_model_hit_rate", "star_join_batch", "star_join_autotune")
+            "cache_model_hit_rate", "star_join_batch", "star_join_autotune", "stream_probe")
 
 
 class StarTuning(ctypes.Structure):
@@ -99,6 +99,8 @@ def load_library(path: str = LIB_PATH):
     lib.star_join_batch.restype = ctypes.c_int
     lib.star_join_autotune.argtypes = [P, P, P, P, I32, P, P, I32, P, I32, P, P, P, P, P, SZ, P]
     lib.star_join_autotune.restype = ctypes.c_int
+    lib.stream_probe.argtypes = [P, SZ, P, P]
+    lib.stream_probe.restype = ctypes.c_int
     lib.skew_max_hot.argtypes = [ctypes.c_int]
     lib.skew_max_hot.restype = I64
     if path == LIB_PATH:
@@ -296,6 +298,18 @@ def cache_model_hit_rate(counts_by_rank: torch.Tensor, cache_lines: int, values_
     _check(lib.cache_model_hit_rate(_ptr(counts_by_rank), counts_by_rank.numel(), _ptr(rank), int(values_per_line),
                                     int(cache_lines), ctypes.byref(out), _ptr(ws), ws.numel(), _stream(dev)))
     return out.value
+
+
+def stream_probe(buf: torch.Tensor) -> torch.Tensor:
+    """One read pass over a contiguous device tensor (16-byte multiple); returns the 64-bit wrapping sum of its
+    32-bit words as a device int64[1] (measurement of the achievable read rate)."""
+    lib = load_library()
+    if not buf.is_contiguous():
+        raise SkewError(SKEW_EINVAL, "buf must be contiguous")
+    out = torch.empty(1, dtype=torch.int64, device=buf.device)
+    nbytes = buf.numel() * buf.element_size()
+    _check(lib.stream_probe(ctypes.c_void_p(buf.data_ptr() if nbytes else 0), nbytes, _ptr(out), _stream(buf.device)))
+    return out
 
 
 @dataclass

@@ -206,3 +206,12 @@ def test_operator_workspace_sizes(lib):
     # bitmap + one round of segments (with the chunk slack) + tables
     assert lib.skew_workspace_bytes(skew.SKEW_OP_SELECT, 1 << 20, 1000) >= 256 + 4 * (1 << 20)
     assert lib.skew_workspace_bytes(skew.SKEW_OP_SELECT, 3_000_000_000, 10) < 4 * 3_000_000_000
+
+
+def test_stream_probe_rejects(lib):
+    ok = ctypes.c_void_p(0x10000)
+    assert lib.stream_probe(ok, 16, NULL, S) == skew.SKEW_EINVAL          # no output
+    assert lib.stream_probe(NULL, 16, A2, S) == skew.SKEW_EINVAL          # no buffer
+    assert lib.stream_probe(ctypes.c_void_p(0x10004), 16, A2, S) == skew.SKEW_EINVAL  # not 16-byte aligned
+    assert lib.stream_probe(ok, 20, A2, S) == skew.SKEW_EINVAL            # not a 16-byte multiple
+    assert lib.stream_probe(ok, 16, ctypes.c_void_p(0x20004), S) == skew.SKEW_EINVAL  # output not 8-byte aligned
