@@ -113,6 +113,7 @@ hipError_t launch_cache_model(const uint32_t *counts_by_rank, int32_t n_keys, co
 constexpr int32_t kMaxStarQueries = 4096;
 size_t star_lds_bytes(int32_t tp, int32_t tc, int32_t nq);
 int32_t star_max_prod_hot(int32_t tc, int32_t nq, const DeviceInfo &dev);
+int32_t star_max_cust_hot(int32_t nq, const DeviceInfo &dev);
 size_t star_workspace_bytes(int32_t n_prod, int32_t n_cust, int32_t nq);
 hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t *qstart, const int32_t *qlt,
                        int32_t nq, const int32_t *price, const int8_t *cat, int32_t n_prod, const int8_t *attr,

@@ -516,7 +516,9 @@ skew_star_tuning star_resolve(const skew_star_tuning *t, int32_t n_prod, int32_t
   r.blocks = t && t->blocks > 0 ? t->blocks : dev.cu_count;
   if (r.cust_hot_rows < 0) r.cust_hot_rows = 0;
   if (r.cust_hot_rows > n_cust) r.cust_hot_rows = n_cust;
-  const int32_t cmax = 65536 < n_cust ? 65536 : n_cust;  // keep LDS for the product prefix
+  int32_t cmax = 131072 < n_cust ? 131072 : n_cust;  // keep some LDS for the product prefix
+  const int32_t cfit = skew::star_max_cust_hot(nq, dev);
+  if (cmax > cfit) cmax = cfit;
   if (r.cust_hot_rows > cmax) r.cust_hot_rows = cmax;
   const int32_t pmax = skew::star_max_prod_hot(r.cust_hot_rows, nq, dev);
   r.prod_hot_rows = t && t->prod_hot_rows >= 0 ? t->prod_hot_rows : pmax;
@@ -567,7 +569,7 @@ int star_join_autotune(const int32_t *prod_keys, const int32_t *cust_keys, const
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
   if (e != hipSuccess) return hip_fail(e, "autotune events");
-  const int32_t cust_cand[] = {0, 8192, 32768, 65536};
+  const int32_t cust_cand[] = {0, 8192, 32768, 65536, 98304, 131072};
   const int32_t tile_cand[] = {65536, 262144, 1048576};
   float best_t = -1.f;
   skew_star_tuning arg{-1, 0, 0, 0};

@@ -301,6 +301,13 @@ int32_t star_max_prod_hot(int32_t tc, int32_t nq, const DeviceInfo &dev) {
   return (int32_t)(((dev.lds_per_block - fixed) / 4) & ~(size_t)3) - 4;
 }
 
+int32_t star_max_cust_hot(int32_t nq, const DeviceInfo &dev) {
+  // with an empty product prefix: bins, query table, reserve, and 16 bytes of padding per table
+  const size_t fixed = star_lds_bytes(0, 0, nq) + 16 + kStaticReserve;
+  if (dev.lds_per_block <= fixed) return 0;
+  return (int32_t)(((dev.lds_per_block - fixed) / 16) * 16);  // whole words of 4 one-byte entries
+}
+
 size_t star_workspace_bytes(int32_t n_prod, int32_t n_cust, int32_t nq) {
   auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
   return r((size_t)n_prod * 4) + r(((size_t)n_cust + 3) / 4 * 4 + 16) + r((size_t)(nq + 1) * 4) + r(16);

@@ -74,6 +74,41 @@ def test_star_batch(batch, tun, layout):
     check(skew.star_join_batch(batch[layout], t), batch["want"])
 
 
+@pytest.fixture(scope="module")
+def wide():
+    """A customer dimension larger than the biggest LDS customer prefix (131072 rows)."""
+    k, n_prod, n_cust = 5, 200_000, 300_000
+    sizes = np.array([70_001, 1_000_003, 5], dtype=np.int64)
+    say(f"star wide batch n_prod={n_prod} n_cust={n_cust}")
+    h = W.host_star_inputs(k, n_prod, n_cust, sizes)
+    lt = np.array([50, 17, 3], dtype=np.int32)
+    start = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    want = [oracle.star_join(h["prod"][a:b], h["cust"][a:b], h["price"], h["category"], h["cust_attr"], lt[q])
+            for q, (a, b) in enumerate(zip(start[:-1], start[1:]))]
+    ident = skew.StarBatch(to_dev(h["prod"]), to_dev(h["cust"]), to_dev(start), to_dev(lt), to_dev(h["price"]),
+                           to_dev(h["category"]), to_dev(h["cust_attr"]))
+    Lp = skew.build_skew_layout(ident.prod_keys, n_prod, ident.price, ident.category)
+    Lc = skew.build_skew_layout(ident.cust_keys, n_cust, None, ident.segment)
+    sk = skew.StarBatch(Lp.fact_recoded, Lc.fact_recoded, ident.query_start, ident.query_cust_lt, Lp.price,
+                        Lp.category, Lc.category)
+    return dict(identity=ident, skew=sk, want=want)
+
+
+@pytest.mark.parametrize("tun", [(-1, 65536, 262_144, 0), (-1, 98_304, 65_536, 0), (-1, 131_072, 262_144, 0),
+                                 (-1, 250_000, 1 << 20, 0), (3, 131_072, 4096, 5)], ids=str)
+@pytest.mark.parametrize("layout", ["skew", "identity"])
+def test_star_wide_customer_prefix(wide, tun, layout):
+    say(f"star wide {layout} tuning={tun}")
+    check(skew.star_join_batch(wide[layout], skew.StarTuning(*tun)), wide["want"])
+
+
+def test_star_autotune_wide(wide):
+    say("star autotune wide")
+    best, ms = skew.star_join_autotune(wide["skew"])
+    assert ms > 0 and best.cust_hot_rows <= 131_072
+    check(skew.star_join_batch(wide["skew"], best), wide["want"])
+
+
 def test_star_autotune(batch):
     say("star autotune")
     best, ms = skew.star_join_autotune(batch["skew"])
