@@ -1,0 +1,100 @@
+"""Parity at the full sizes the bench times, in the same launch configuration.
+
+The join workload (1e7-row dimension, 1e9 Zipf(1.0) fact keys, 16 groups) and
+the group-by workload (1e6 groups, 5e8 Zipf(1.1) rows, values U[0,1000]) are
+generated on the device from the same seeds as the bench; the layout is built,
+and the query runs with the library's default hot prefix (SKEW_HOT_AUTO) on
+the frequency-ordered layout and with no prefix on the identity layout.  The
+oracle computes every output from the host copy of the identity-layout
+columns; the GPU results must equal it exactly.  The layout itself is checked
+through properties that hold at any size.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1910_10063_amd import skew
+from paper_1910_10063_amd import workload as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+DEV = "cuda"
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def check_layout_properties(L, n_keys, n_fact):
+    perm, rank, cbr = host(L.perm), host(L.rank), host(L.counts_by_rank).astype(np.int64)
+    assert np.array_equal(np.sort(perm), np.arange(n_keys, dtype=np.int32)), "perm is a permutation"
+    assert np.array_equal(rank[perm], np.arange(n_keys, dtype=np.int32)), "rank inverts perm"
+    assert cbr.sum() == n_fact, "frequencies sum to the column length"
+    assert (np.diff(cbr) <= 0).all(), "frequencies do not increase along perm"
+    ties = np.flatnonzero(np.diff(cbr) == 0)
+    assert (perm[ties] < perm[ties + 1]).all(), "equal frequencies in ascending key order"
+
+
+def test_join_full_size():
+    N, F, S = 10_000_000, 1_000_000_000, 1.0
+    say(f"join full size N={N} F={F} s={S}")
+    d = W.device_join_inputs(2, N, F, S, DEV)
+    L = skew.build_skew_layout(d["fact"], N, d["price"], d["category"])
+    check_layout_properties(L, N, F)
+    # sampled recode: C'[j] = rank[C[j]]
+    idx = torch.from_numpy(np.random.default_rng(1).integers(0, F, 1_000_000)).to(DEV)
+    assert torch.equal(L.fact_recoded[idx], L.rank[d["fact"][idx].long()])
+    es, ec = oracle.fk_join_aggregate(host(d["fact"]), host(d["price"]), host(d["category"]), 16, True)
+    ws = skew.workspace(skew.SKEW_OP_JOIN, F, N, DEV)
+    s, c = skew.fk_join_aggregate(L.fact_recoded, L.price, L.category, 16, True, hot_rows=skew.SKEW_HOT_AUTO, ws=ws)
+    assert (host(s) == es).all() and (host(c) == ec).all(), "skew layout"
+    s, c = skew.fk_join_aggregate(d["fact"], d["price"], d["category"], 16, True, hot_rows=0, ws=ws)
+    assert (host(s) == es).all() and (host(c) == ec).all(), "identity layout"
+    assert skew.query_status(ws) == skew.SKEW_OK
+    del d, L, ws, idx
+    torch.cuda.empty_cache()
+
+
+def test_group_by_full_size():
+    M, F, S = 1_000_000, 500_000_000, 1.1
+    say(f"group-by full size M={M} F={F} s={S}")
+    g = W.device_group_inputs(3, M, F, S, device=DEV)
+    L = skew.build_skew_layout(g["keys"], M)
+    check_layout_properties(L, M, F)
+    es, ec, inv = oracle.group_aggregate(host(g["keys"]), host(g["vals"]), M)
+    assert inv == 0
+    ws = skew.workspace(skew.SKEW_OP_GROUP, F, M, DEV)
+    s, c = skew.group_aggregate(L.fact_recoded, g["vals"], M, hot_groups=skew.SKEW_HOT_AUTO, perm=L.perm, ws=ws)
+    assert (host(s) == es).all() and (host(c) == ec).all(), "skew layout"
+    s, c = skew.group_aggregate(g["keys"], g["vals"], M, hot_groups=0, ws=ws)
+    assert (host(s) == es).all() and (host(c) == ec).all(), "identity layout"
+    assert skew.query_status(ws) == skew.SKEW_OK
+    del g, L, ws
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("S", [0.0, 0.5, 1.5])
+def test_join_zipf_sweep_one_round(S):
+    """The other exponents of the sweep on a 1e7-row dimension, one full round of 2^28 keys plus a ragged tail."""
+    N, F = 10_000_000, (1 << 28) + 3
+    say(f"join sweep N={N} F={F} s={S}")
+    d = W.device_join_inputs(2, N, F, S, DEV)
+    L = skew.build_skew_layout(d["fact"], N, d["price"], d["category"])
+    check_layout_properties(L, N, F)
+    es, ec = oracle.fk_join_aggregate(host(d["fact"]), host(d["price"]), host(d["category"]), 16, True)
+    ws = skew.workspace(skew.SKEW_OP_JOIN, F, N, DEV)
+    for keys, pr, ca, t in ((L.fact_recoded, L.price, L.category, skew.SKEW_HOT_AUTO),
+                            (d["fact"], d["price"], d["category"], 0)):
+        s, c = skew.fk_join_aggregate(keys, pr, ca, 16, True, hot_rows=t, ws=ws)
+        assert (host(s) == es).all() and (host(c) == ec).all(), t
+    del d, L, ws
+    torch.cuda.empty_cache()
