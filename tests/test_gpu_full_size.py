@@ -98,3 +98,38 @@ def test_join_zipf_sweep_one_round(S):
         assert (host(s) == es).all() and (host(c) == ec).all(), t
     del d, L, ws
     torch.cuda.empty_cache()
+
+
+def test_star_batch_full_size():
+    """The bench's batch: 64 queries, fact sizes log-uniform in [1e5, 1e8] rows, product dimension 1e7 rows
+    (Zipf 1.0), customer dimension 2e6 rows (Zipf 0.8), with the autotuned tuning, replayed from a HIP graph."""
+    k, n_prod, n_cust, nq = 4, 10_000_000, 2_000_000, 64
+    sizes, lt, start = W.star_batch_spec(k, nq, 1e5, 1e8)
+    say(f"star batch full size rows={int(start[-1])}")
+    d = W.device_star_inputs(k, n_prod, n_cust, sizes, device=DEV)
+    qs, ql = torch.from_numpy(start).to(DEV), torch.from_numpy(lt).to(DEV)
+    Lp = skew.build_skew_layout(d["prod"], n_prod, d["price"], d["category"])
+    Lc = skew.build_skew_layout(d["cust"], n_cust, None, d["cust_attr"])
+    sk = skew.StarBatch(Lp.fact_recoded, Lc.fact_recoded, qs, ql, Lp.price, Lp.category, Lc.category)
+    ws = skew.star_workspace(sk)
+    out = (torch.empty(nq, 16, dtype=torch.int64, device=DEV), torch.empty(nq, 16, dtype=torch.int64, device=DEV))
+    best, _ = skew.star_join_autotune(sk, ws=ws)
+    skew.star_join_batch(sk, best, ws=ws, out=out)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        skew.star_join_batch(sk, best, ws=ws, out=out)
+    prod, cust = host(d["prod"]), host(d["cust"])
+    price, cat, attr = host(d["price"]), host(d["category"]), host(d["cust_attr"])
+    want = [oracle.star_join(prod[int(start[q]):int(start[q + 1])], cust[int(start[q]):int(start[q + 1])], price, cat,
+                             attr, int(lt[q])) for q in range(nq)]
+    for replay in range(2):  # eager work and a synchronisation between the replays
+        out[0].fill_(-1)
+        out[1].fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        s, c = host(out[0]), host(out[1])
+        for q in range(nq):
+            assert (s[q] == want[q][0]).all() and (c[q] == want[q][1]).all(), (replay, q)
+    del d, Lp, Lc, sk, ws, g
+    torch.cuda.empty_cache()
