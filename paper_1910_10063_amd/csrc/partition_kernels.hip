@@ -270,16 +270,144 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
 // segment and counts it in its slice (k >> 15); the shared plan and scatter
 // above order the keys by slice as 2-byte offsets; pass 3 counts every slice
 // in LDS and adds the counts into the histogram.
+//
+// Large columns first count a sample (their first kHotSample keys) this
+// way, take the keys whose sample count is highest (at most kHotMax of them,
+// the likely hot keys) into a hash table, and count the rest of the column
+// with that table in LDS: a key found there is counted in an LDS counter of
+// its slot, and only the others are partitioned.  A key is counted exactly
+// once either way, so the counts do not depend on which keys the table holds.
 // ---------------------------------------------------------------------------
 constexpr int kHistThreads = 1024;
 constexpr int kHistVecs = 4;
+constexpr int kHotBucketBits = 12;
+constexpr int kHotBuckets = 1 << kHotBucketBits;  // 4-slot buckets
+constexpr int kHotSlots = 4 * kHotBuckets;         // 16384 slots: keys 64 KB + counters 64 KB of LDS
+constexpr int kHotMax = 3 * kHotBuckets;           // keys offered to the table (75 % of the slots)
+constexpr int kCountBins = 256;                    // 8 bins per power of two of a count
+constexpr int64_t kHotSample = 1LL << 24;          // keys counted before the table is chosen
+constexpr int64_t kHotMinFact = 1LL << 26;         // smaller columns skip the table
 
+__device__ __forceinline__ uint32_t hot_bucket(uint32_t k) { return (k * 0x9E3779B1u) >> (32 - kHotBucketBits); }
+
+// Bin of a count c >= 1: floor(log2 c) and the next three bits, so bins rise with c.
+__device__ __forceinline__ int count_bin(uint32_t c) {
+  const int e = 31 - __clz(c);
+  const uint32_t m = e >= 3 ? (c >> (e - 3)) & 7u : (c << (3 - e)) & 7u;
+  return e * 8 + (int)m;
+}
+
+// Number of keys and their total count per count bin.
+__global__ void count_bins_kernel(const uint32_t *__restrict__ counts, int32_t n_keys, uint32_t *__restrict__ bin_n,
+                                  unsigned long long *__restrict__ bin_sum) {
+  __shared__ uint32_t ln[kCountBins];
+  __shared__ unsigned long long ls[kCountBins];
+  for (int i = threadIdx.x; i < kCountBins; i += blockDim.x) {
+    ln[i] = 0;
+    ls[i] = 0;
+  }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_keys; k += stride) {
+    const uint32_t c = counts[k];
+    if (c) {
+      const int b = count_bin(c);
+      atomicAdd(&ln[b], 1u);
+      atomicAdd(&ls[b], (unsigned long long)c);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kCountBins; i += blockDim.x)
+    if (ln[i]) {
+      atomicAdd(&bin_n[i], ln[i]);
+      atomicAdd(&bin_sum[i], ls[i]);
+    }
+}
+
+// The lowest bin from which on at most kHotMax keys lie; no bin (kCountBins)
+// when those keys cover less than an eighth of the sample, since the table
+// would then cost more lookups than it saves.  Clears the key count.
+__global__ void pick_hot_kernel(const uint32_t *__restrict__ bin_n, const unsigned long long *__restrict__ bin_sum,
+                                uint64_t sample, int32_t *__restrict__ tau, uint32_t *__restrict__ hot_n) {
+  if (threadIdx.x != 0) return;
+  uint32_t keys = 0;
+  unsigned long long cover = 0;
+  int b = kCountBins;
+  while (b > 0 && keys + bin_n[b - 1] <= (uint32_t)kHotMax) {
+    --b;
+    keys += bin_n[b];
+    cover += bin_sum[b];
+  }
+  *tau = (keys > 0 && cover * 8 >= sample) ? b : kCountBins;
+  *hot_n = 0;
+}
+
+__global__ void collect_hot_kernel(const uint32_t *__restrict__ counts, int32_t n_keys, const int32_t *__restrict__ tau,
+                                   int32_t *__restrict__ hot_keys, uint32_t *__restrict__ hot_n) {
+  const int t = *tau;
+  if (t >= kCountBins) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_keys; k += stride) {
+    const uint32_t c = counts[k];
+    if (c && count_bin(c) >= t) {
+      const uint32_t i = atomicAdd(hot_n, 1u);
+      if (i < (uint32_t)kHotMax) hot_keys[i] = (int32_t)k;
+    }
+  }
+}
+
+// One workgroup inserts the chosen keys into the 4-slot buckets (a key whose
+// bucket is full stays out) and writes the table; every workgroup of the
+// split then loads the same table.
+__global__ __launch_bounds__(kHistThreads) void hot_table_kernel(const int32_t *__restrict__ hot_keys,
+                                                                 const uint32_t *__restrict__ hot_n,
+                                                                 int32_t *__restrict__ table) {
+  __shared__ int32_t tk[kHotSlots];
+  for (int i = threadIdx.x; i < kHotSlots; i += blockDim.x) tk[i] = -1;
+  __syncthreads();
+  const uint32_t n = *hot_n < (uint32_t)kHotMax ? *hot_n : (uint32_t)kHotMax;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const int32_t k = hot_keys[i];
+    const uint32_t b = hot_bucket((uint32_t)k) * 4;
+    for (int j = 0; j < 4; ++j)
+      if (atomicCAS(&tk[b + j], -1, k) == -1) break;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHotSlots; i += blockDim.x) table[i] = tk[i];
+}
+
+// Per-slot counts of all workgroups, added into the histogram.
+__global__ void hot_reduce_kernel(const uint32_t *__restrict__ partial, int32_t blocks, const int32_t *__restrict__ table,
+                                  uint32_t *__restrict__ counts) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= kHotSlots) return;
+  const int32_t k = table[s];
+  if (k < 0) return;
+  uint32_t c = 0;
+  for (int b = 0; b < blocks; ++b) c += partial[(int64_t)b * kHotSlots + s];
+  if (c) global_add_u32(&counts[k], c);
+}
+
+// HOT: keys found in the hot table are counted in LDS (partial[block][slot]
+// at the end) instead of being partitioned.
+template <bool HOT>
 __global__ __launch_bounds__(kHistThreads) void hist_split_kernel(const int32_t *__restrict__ keys, int64_t n,
                                                                   int32_t n_keys, int32_t P, int32_t *__restrict__ seg,
                                                                   int64_t seg_cap, uint32_t *__restrict__ seg_count,
-                                                                  uint32_t *__restrict__ hist, int32_t *flag) {
+                                                                  uint32_t *__restrict__ hist, int32_t *flag,
+                                                                  const int32_t *__restrict__ table,
+                                                                  const int32_t *__restrict__ tau,
+                                                                  uint32_t *__restrict__ partial) {
   __shared__ uint32_t lhist[kMaxSlices + kWave + 1];  // slice counts | per-lane sinks | item count
+  extern __shared__ __align__(16) unsigned char smem[];
+  int32_t *tkeys = reinterpret_cast<int32_t *>(smem);                  // HOT: [kHotSlots]
+  uint32_t *tcnt = reinterpret_cast<uint32_t *>(tkeys + kHotSlots);   // HOT: [kHotSlots + kWave]
   for (int p = threadIdx.x; p < P + kWave + 1; p += blockDim.x) lhist[p] = 0;
+  const bool use_hot = HOT && *tau < kCountBins;  // same for every thread
+  if (use_hot) {
+    for (int i = threadIdx.x; i < kHotSlots; i += blockDim.x) tkeys[i] = table[i];
+    for (int i = threadIdx.x; i < kHotSlots + kWave; i += blockDim.x) tcnt[i] = 0;
+  }
   __syncthreads();
   ColdSink o;
   o.count = &lhist[P + kWave];
@@ -297,6 +425,18 @@ __global__ __launch_bounds__(kHistThreads) void hist_split_kernel(const int32_t 
       in[i] = ok[i] && k[i] < nk;
       bad |= ok[i] && k[i] >= nk;
     }
+    if (use_hot) {
+#pragma unroll
+      for (int i = 0; i < 4 * kHistVecs; ++i) {
+        const uint32_t b = hot_bucket(k[i]) * 4;
+        const i32x4 ks = *reinterpret_cast<const i32x4 *>(tkeys + b);
+        const bool h0 = ks.x == (int32_t)k[i], h1 = ks.y == (int32_t)k[i], h2 = ks.z == (int32_t)k[i];
+        const bool hit = in[i] && (h0 || h1 || h2 || ks.w == (int32_t)k[i]);
+        const uint32_t slot = h0 ? b : (h1 ? b + 1 : (h2 ? b + 2 : b + 3));
+        lds_add_u32(&tcnt[hit ? slot : (uint32_t)kHotSlots + lane_id()], 1u);
+        in[i] = in[i] && !hit;
+      }
+    }
     cold_append(o, k, in, [&](int i, int32_t idx) { buffer_store_record((int32_t)k[i], out, idx, 0, 0, 0); });
   };
   const Split4 sp = split4(keys, n);
@@ -305,10 +445,16 @@ __global__ __launch_bounds__(kHistThreads) void hist_split_kernel(const int32_t 
     if (blockIdx.x == 0 && threadIdx.x < sp.head) i = threadIdx.x;
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x >= kWave && threadIdx.x - kWave < n - sp.tail)
       i = sp.tail + threadIdx.x - kWave;
-    const uint32_t k[1] = {i >= 0 ? (uint32_t)keys[i] : 0u};
-    const bool in[1] = {i >= 0 && k[0] < nk};
-    bad |= i >= 0 && k[0] >= nk;
-    cold_append(o, k, in, [&](int, int32_t idx) { buffer_store_record((int32_t)k[0], out, idx, 0, 0, 0); });
+    uint32_t k1[4 * kHistVecs];
+    bool ok1[4 * kHistVecs];
+#pragma unroll
+    for (int j = 0; j < 4 * kHistVecs; ++j) {
+      k1[j] = 0;
+      ok1[j] = false;
+    }
+    k1[0] = i >= 0 ? (uint32_t)keys[i] : 0u;
+    ok1[0] = i >= 0;
+    put(k1, ok1);
   }
   const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
   const int64_t per = (sp.nvec + gridDim.x - 1) / gridDim.x;
@@ -364,6 +510,8 @@ __global__ __launch_bounds__(kHistThreads) void hist_split_kernel(const int32_t 
   __syncthreads();
   if (threadIdx.x == 0) seg_count[blockIdx.x] = *o.count < seg_cap ? *o.count : (uint32_t)seg_cap;
   for (int p = threadIdx.x; p < P; p += blockDim.x) hist[(int64_t)p * gridDim.x + blockIdx.x] = lhist[p];
+  if (use_hot)
+    for (int i = threadIdx.x; i < kHotSlots; i += blockDim.x) partial[(int64_t)blockIdx.x * kHotSlots + i] = tcnt[i];
 }
 
 // Pass 3.  Within a wave the value of the first active lane is often the
@@ -492,11 +640,19 @@ HistPlan hist_plan(int64_t n_fact, int32_t n_keys, const DeviceInfo &dev) {
   return pl;
 }
 
+// Hot-table region: count bins, the cut, the chosen keys, the table and the
+// per-workgroup slot counts.
+static size_t hot_region_bytes(int32_t blocks) {
+  auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return r((size_t)kCountBins * 4) + r((size_t)kCountBins * 8) + r(16) + r((size_t)kHotMax * 4) +
+         r((size_t)kHotSlots * 4) + r((size_t)blocks * kHotSlots * 4);
+}
+
 size_t hist_partition_bytes(const HistPlan &pl) {
   auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const int32_t P = pl.slices > 0 ? pl.slices : 1;
   return r((size_t)pl.blocks * pl.seg_cap * 4) + r((size_t)pl.round * 2 + 16) + r((size_t)P * pl.blocks * 4) +
-         r((size_t)P * 4) + r(4) + r((size_t)pl.blocks * 4) + r((size_t)(P + 1) * 4);
+         r((size_t)P * 4) + r(4) + r((size_t)pl.blocks * 4) + r((size_t)(P + 1) * 4) + hot_region_bytes(pl.blocks);
 }
 
 hipError_t launch_histogram_partitioned(const int32_t *keys, int64_t n_fact, int32_t n_keys, uint32_t *counts,
@@ -517,25 +673,78 @@ hipError_t launch_histogram_partitioned(const int32_t *keys, int64_t n_fact, int
   tab.seg_count = (uint32_t *)ws;
   ws += r((size_t)pl.blocks * 4);
   tab.slice_off = (uint32_t *)ws;
+  ws += r((size_t)(pl.slices + 1) * 4);
+  uint32_t *bin_n = (uint32_t *)ws;
+  ws += r((size_t)kCountBins * 4);
+  unsigned long long *bin_sum = (unsigned long long *)ws;
+  ws += r((size_t)kCountBins * 8);
+  int32_t *tau = (int32_t *)ws;
+  uint32_t *hot_n = (uint32_t *)(ws + 4);
+  ws += r(16);
+  int32_t *hot_keys = (int32_t *)ws;
+  ws += r((size_t)kHotMax * 4);
+  int32_t *table = (int32_t *)ws;
+  ws += r((size_t)kHotSlots * 4);
+  uint32_t *partial = (uint32_t *)ws;
+
   const size_t lds3 = ((size_t)(1 << kHistSliceShift) + kWave + pl.slices + 1) * 4;
+  const size_t lds_hot = (size_t)(2 * kHotSlots + kWave) * 4;
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(hist_slice_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds3);
-  for (int64_t off = 0; off < n_fact; off += pl.round) {
-    const int64_t n = n_fact - off < pl.round ? n_fact - off : pl.round;
-    hipLaunchKernelGGL(hist_split_kernel, dim3(pl.blocks), dim3(kHistThreads), 0, s, keys + off, n, n_keys, pl.slices,
-                       seg, pl.seg_cap, tab.seg_count, tab.hist, flag);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = launch_partition_plan(tab, pl.slices, pl.blocks, s);
-    if (e == hipSuccess)
-      e = launch_partition_scatter(tab, pl.slices, pl.blocks, seg, nullptr, pl.seg_cap, 0, kHistSliceShift, items,
-                                   nullptr, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hist_slice_kernel, dim3(pl.blocks), dim3(kHistThreads), lds3, s, items, tab.slice_off,
-                       pl.slices, n_keys, counts);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(hist_split_kernel<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_hot);
+  // one round of the partitioned count over keys [lo, hi), with or without the hot table
+  auto count_rounds = [&](int64_t lo, int64_t hi, bool hot) -> hipError_t {
+    for (int64_t off = lo; off < hi; off += pl.round) {
+      const int64_t n = hi - off < pl.round ? hi - off : pl.round;
+      if (hot)
+        hipLaunchKernelGGL(hist_split_kernel<true>, dim3(pl.blocks), dim3(kHistThreads), lds_hot, s, keys + off, n,
+                           n_keys, pl.slices, seg, pl.seg_cap, tab.seg_count, tab.hist, flag, table, tau, partial);
+      else
+        hipLaunchKernelGGL(hist_split_kernel<false>, dim3(pl.blocks), dim3(kHistThreads), 0, s, keys + off, n, n_keys,
+                           pl.slices, seg, pl.seg_cap, tab.seg_count, tab.hist, flag, table, tau, partial);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = launch_partition_plan(tab, pl.slices, pl.blocks, s);
+      if (e == hipSuccess)
+        e = launch_partition_scatter(tab, pl.slices, pl.blocks, seg, nullptr, pl.seg_cap, 0, kHistSliceShift, items,
+                                     nullptr, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(hist_slice_kernel, dim3(pl.blocks), dim3(kHistThreads), lds3, s, items, tab.slice_off,
+                         pl.slices, n_keys, counts);
+      e = hipGetLastError();
+      if (e == hipSuccess && hot) {
+        hipLaunchKernelGGL(hot_reduce_kernel, dim3(kHotSlots / 256), dim3(256), 0, s, partial, pl.blocks, table,
+                           counts);
+        e = hipGetLastError();
+      }
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  if (n_fact < kHotMinFact) return count_rounds(0, n_fact, false);
+  // the sample, then the table of its most frequent keys, then the rest of the column through the table
+  hipError_t e = count_rounds(0, kHotSample, false);
+  if (e == hipSuccess) e = launch_fill_u32(bin_n, kCountBins, 0u, s);
+  if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(bin_sum), 2 * kCountBins, 0u, s);
+  const int grid = (int)((n_keys + 255) / 256 < (int64_t)pl.blocks * 8 ? (n_keys + 255) / 256 : pl.blocks * 8);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(count_bins_kernel, dim3(grid), dim3(256), 0, s, counts, n_keys, bin_n, bin_sum);
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(pick_hot_kernel, dim3(1), dim3(64), 0, s, bin_n, bin_sum, (uint64_t)kHotSample, tau, hot_n);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(collect_hot_kernel, dim3(grid), dim3(256), 0, s, counts, n_keys, tau, hot_keys, hot_n);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(hot_table_kernel, dim3(1), dim3(kHistThreads), 0, s, hot_keys, hot_n, table);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = count_rounds(kHotSample, n_fact, true);
+  return e;
 }
 
 }  // namespace skew

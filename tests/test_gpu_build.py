@@ -106,6 +106,35 @@ def test_partitioned_build_three_rounds():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("N,s,offset", [(1_000_000, 1.0, 0), (10_000_000, 1.0, 1), (3_000_000, 0.0, 0),
+                                        (5_000, 1.5, 3), (40_000_000, 1.0, 2)])
+def test_build_with_hot_table(N, s, offset):
+    """Columns of at least 2^26 keys count a sample first, then the rest with an LDS table of the keys most frequent
+    in the sample; the counts (and the layout) must not depend on the table: skewed keys (table used), uniform keys
+    (table skipped), a domain smaller than the table, and a domain too large for the slice table."""
+    F = (1 << 26) + 12_345
+    say(f"build with hot table N={N} s={s} offset={offset}")
+    h = W.host_join_inputs(11, N, F + offset, s)
+    fact = h["fact"][offset:]
+    ref = oracle.build_layout(fact, N, h["price"], h["category"])
+    buf = to_dev(h["fact"])
+    L = skew.build_skew_layout(buf[offset:], N, to_dev(h["price"]), to_dev(h["category"]))
+    check(L, ref)
+
+
+def test_build_with_hot_table_out_of_range():
+    """An out-of-range key after the sample, where the table is in use, is still reported."""
+    N, F = 100_000, (1 << 26) + 5
+    say("build with hot table, out-of-range keys")
+    h = W.host_join_inputs(12, N, F, 1.0)
+    for pos, bad in ((F - 3, N), ((1 << 25), -7)):
+        f = h["fact"].copy()
+        f[pos] = bad
+        with pytest.raises(skew.SkewError) as e:
+            skew.build_skew_layout(to_dev(f), N)
+        assert e.value.code == skew.SKEW_ERANGE
+
+
 @pytest.mark.parametrize("N,s,in_place,offset", [(100, 1.0, False, 0), (2_000_000, 1.0, True, 0),
                                                  (10_000_000, 0.0, False, 1), (50_000, 1.5, True, 3)])
 def test_recode_hot_keys(N, s, in_place, offset):
