@@ -512,12 +512,14 @@ int32_t join_max_hot_rows(int groups, const DeviceInfo &dev) {
 
 JoinPlan join_plan(int64_t n_fact, int32_t n_rows, int32_t t, int groups, const DeviceInfo &dev) {
   JoinPlan pl;
-  // at least 16 workgroups, so that no accumulator bin sees 2^19 rows of a round
-  pl.blocks = dev.cu_count > 16 ? dev.cu_count : 16;
+  // at least 32 workgroups, so that no accumulator bin sees 2^19 rows of a round (a bin takes the rows of one
+  // lane position of a workgroup: fewer than 2^29 / 32 / 64 = 2^18 rows)
+  pl.blocks = dev.cu_count > 32 ? dev.cu_count : 32;
+  static_assert(kJoinMaxRound / 32 / kWave + 64 < (1LL << 19), "join bins must see fewer than 2^19 rows");
   pl.wshift = kJoinSliceShift;
   const int64_t cold_rows = (int64_t)n_rows - t;
   pl.slices = cold_rows > 0 ? (int32_t)((cold_rows + (1 << pl.wshift) - 1) >> pl.wshift) : 0;
-  pl.round = n_fact < kMaxRound ? n_fact : kMaxRound;
+  pl.round = n_fact < kJoinMaxRound ? n_fact : kJoinMaxRound;
   const int64_t nvec = (pl.round + 3) / 4 + 1;
   pl.seg_cap = 4 * ((nvec + pl.blocks - 1) / pl.blocks) + 8;
   (void)groups;

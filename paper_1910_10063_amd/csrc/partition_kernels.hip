@@ -297,7 +297,29 @@ __device__ __forceinline__ int count_bin(uint32_t c) {
   return e * 8 + (int)m;
 }
 
-// Number of keys and their total count per count bin.
+// Counts [0, n_keys) four at a time (16-byte loads; n_keys is padded to a
+// multiple of 4 by reading the tail one by one).
+template <class F>
+__device__ __forceinline__ void for_each_count(const uint32_t *__restrict__ counts, int32_t n_keys, F f) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nv = n_keys / 4;
+  const uint4 *v = reinterpret_cast<const uint4 *>(counts);  // the histogram is 256-byte aligned
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+    const uint4 c = v[i];
+    f(4 * i, c.x);
+    f(4 * i + 1, c.y);
+    f(4 * i + 2, c.z);
+    f(4 * i + 3, c.w);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (unsigned)(n_keys - 4 * nv))
+    f(4 * nv + threadIdx.x, counts[4 * nv + threadIdx.x]);
+}
+
+// Sample counts below this cannot make a table worth its lookups (12288 keys
+// of fewer than 4 sample rows each cover under 0.3 % of a 2^24-key sample).
+constexpr uint32_t kHotMinCount = 4;
+
+// Number of keys and their total count per count bin (counts >= kHotMinCount).
 __global__ void count_bins_kernel(const uint32_t *__restrict__ counts, int32_t n_keys, uint32_t *__restrict__ bin_n,
                                   unsigned long long *__restrict__ bin_sum) {
   __shared__ uint32_t ln[kCountBins];
@@ -307,15 +329,13 @@ __global__ void count_bins_kernel(const uint32_t *__restrict__ counts, int32_t n
     ls[i] = 0;
   }
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_keys; k += stride) {
-    const uint32_t c = counts[k];
-    if (c) {
+  for_each_count(counts, n_keys, [&](int64_t, uint32_t c) {
+    if (c >= kHotMinCount) {
       const int b = count_bin(c);
       atomicAdd(&ln[b], 1u);
       atomicAdd(&ls[b], (unsigned long long)c);
     }
-  }
+  });
   __syncthreads();
   for (int i = threadIdx.x; i < kCountBins; i += blockDim.x)
     if (ln[i]) {
@@ -346,14 +366,12 @@ __global__ void collect_hot_kernel(const uint32_t *__restrict__ counts, int32_t 
                                    int32_t *__restrict__ hot_keys, uint32_t *__restrict__ hot_n) {
   const int t = *tau;
   if (t >= kCountBins) return;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_keys; k += stride) {
-    const uint32_t c = counts[k];
-    if (c && count_bin(c) >= t) {
+  for_each_count(counts, n_keys, [&](int64_t k, uint32_t c) {
+    if (c >= kHotMinCount && count_bin(c) >= t) {
       const uint32_t i = atomicAdd(hot_n, 1u);
       if (i < (uint32_t)kHotMax) hot_keys[i] = (int32_t)k;
     }
-  }
+  });
 }
 
 // One workgroup inserts the chosen keys into the 4-slot buckets (a key whose
@@ -376,15 +394,21 @@ __global__ __launch_bounds__(kHistThreads) void hot_table_kernel(const int32_t *
   for (int i = threadIdx.x; i < kHotSlots; i += blockDim.x) table[i] = tk[i];
 }
 
-// Per-slot counts of all workgroups, added into the histogram.
+// Per-slot counts of the workgroups, added into the histogram: grid.y cuts
+// the workgroups into groups of kReduceRows, each added with one atomic.
+constexpr int kReduceRows = 16;
+
 __global__ void hot_reduce_kernel(const uint32_t *__restrict__ partial, int32_t blocks, const int32_t *__restrict__ table,
                                   uint32_t *__restrict__ counts) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= kHotSlots) return;
   const int32_t k = table[s];
   if (k < 0) return;
+  const int b0 = blockIdx.y * kReduceRows;
+  const int b1 = b0 + kReduceRows < blocks ? b0 + kReduceRows : blocks;
   uint32_t c = 0;
-  for (int b = 0; b < blocks; ++b) c += partial[(int64_t)b * kHotSlots + s];
+#pragma unroll 8
+  for (int b = b0; b < b1; ++b) c += partial[(int64_t)b * kHotSlots + s];
   if (c) global_add_u32(&counts[k], c);
 }
 
@@ -713,8 +737,8 @@ hipError_t launch_histogram_partitioned(const int32_t *keys, int64_t n_fact, int
                          pl.slices, n_keys, counts);
       e = hipGetLastError();
       if (e == hipSuccess && hot) {
-        hipLaunchKernelGGL(hot_reduce_kernel, dim3(kHotSlots / 256), dim3(256), 0, s, partial, pl.blocks, table,
-                           counts);
+        hipLaunchKernelGGL(hot_reduce_kernel, dim3(kHotSlots / 256, (pl.blocks + kReduceRows - 1) / kReduceRows),
+                           dim3(256), 0, s, partial, pl.blocks, table, counts);
         e = hipGetLastError();
       }
       if (e != hipSuccess) return e;

@@ -84,7 +84,7 @@ def test_group_by_full_size():
 
 @pytest.mark.parametrize("S", [0.0, 0.5, 1.5])
 def test_join_zipf_sweep_one_round(S):
-    """The other exponents of the sweep on a 1e7-row dimension, one full round of 2^28 keys plus a ragged tail."""
+    """The other exponents of the sweep on a 1e7-row dimension, 2^28 + 3 keys (a ragged tail)."""
     N, F = 10_000_000, (1 << 28) + 3
     say(f"join sweep N={N} F={F} s={S}")
     d = W.device_join_inputs(2, N, F, S, DEV)

@@ -93,7 +93,7 @@ def test_materialize_out_of_range_keys():
 
 @pytest.mark.slow
 def test_materialize_full_size_sampled():
-    """1e7-row dimension, 2^28 + 5 Zipf(1.0) keys (one full round of the join), sampled rows."""
+    """1e7-row dimension, 2^28 + 5 Zipf(1.0) keys, sampled rows."""
     N, F = 10_000_000, (1 << 28) + 5
     say(f"materialize full size N={N} F={F}")
     d = W.device_join_inputs(2, N, F, 1.0, DEV)
