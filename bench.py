@@ -29,6 +29,30 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "fact tuples/s and % of HBM roofline, skew layout vs identity layout (bit-exact)"
+
+# The paper's own results for this path, reported beside ours as context only: they were measured on CPUs
+# (Section 5, hardware table: Skylake Xeon 8175M, 24 cores x 2 SMT, 2.5 GHz, 60 GB/s; Xeon Phi 7210, 64 cores
+# x 4 SMT, 1.3 GHz, 55 GB/s), with 4-byte keys, on Zipf columns of 1e9 facts and 128M keys unless noted.
+PAPER_CONTEXT = {
+    "hardware": {"skylake": "Xeon 8175M, 24 cores x 2 SMT, 2.5 GHz, 33 MB L3, 60 GB/s",
+                 "phi": "Xeon Phi 7210, 64 cores x 4 SMT, 1.3 GHz, no L3, 55 GB/s"},
+    "speedups_freq_vs_rand": [
+        {"query": "Q1 materialize, SIMD, z=1", "speedup": ">1.2x on both", "where": "Section 5.1"},
+        {"query": "Q1 materialize with software prefetch, z=1", "speedup": "3x", "hardware": "phi",
+         "where": "Section 5.1"},
+        {"query": "Q1 materialize, multithreaded", "speedup": ">1.3x", "hardware": "both, up to 48/256 threads",
+         "where": "Section 5.1"},
+        {"query": "Q2 select, multithreaded", "speedup": "1.4-2.2x (phi), 1.3-1.8x (skylake)", "where": "Section 5.1"},
+        {"query": "top-4k heavy hitters vs the full aggregate, z=0.5", "speedup": "8.6x (phi), 6.6x (skylake)",
+         "where": "Section 5.1"},
+        {"query": "hybrid aggregation vs independent per-thread buffers", "speedup": "4.7x (skylake, 48 threads), "
+         "10.4x (phi, 256 threads)", "where": "Section 5.1"},
+        {"query": "Pageview Q1 / Q2 / Q3 / top-4k, one thread", "speedup": "1.5x / 2.2x / 1.3x / 4.0x",
+         "hardware": "skylake", "where": "Section 5.2"},
+    ],
+    "index_build": "a Q3 plus a Q1 on the rand layout: a few seconds with all threads (Section 5.1)",
+    "gpu_numbers": None,
+}
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "join_split_traffic.json")
 # sources of the dominant kernel (the join's pass 1): its counters stay valid while these are unchanged
@@ -252,6 +276,7 @@ def main():
                              "category": W.category_seed(k)}},
         "roofline": roofline,
         "query_roofline": query_roofline,
+        "paper_context": PAPER_CONTEXT,
         "read_probe": {"kernel": "stream_probe", "bytes": 4.0 * F, "ms": round(ms_probe, 4),
                        "GB_per_s": round(probe_gbs, 1), "frac_of_peak": round(probe_gbs / HBM_PEAK_GBS, 4)},
         "identity": {"value": F / (ms_ident * 1e-3), "ms_per_step": ms_ident} if ms_ident else None,
