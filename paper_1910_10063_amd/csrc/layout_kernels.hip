@@ -276,26 +276,47 @@ __global__ __launch_bounds__(kRecodeThreads) void recode_kernel(const int32_t *k
 // ---------------------------------------------------------------------------
 // Recode with the hot keys in LDS.  Once the ranks are known, the hottest
 // keys are known too (perm[0..T)): every workgroup inserts them, hottest
-// first, into an LDS hash table of 4-slot buckets (key -> rank; a key whose
-// bucket is full stays out), and each fact key is looked up there with one
-// 16-byte LDS read before falling back to the rank array in global memory.
+// first, into an LDS hash table of 4-slot buckets (a key whose bucket is full
+// stays out), and each fact key is looked up there with one 16-byte LDS read
+// before falling back to the rank array in global memory.  A slot is one
+// word, (key >> 13) << 16 | rank, and the bucket is the low 13 bits of the
+// key (8192 buckets x 4 slots = 128 KB), so the table serves key domains
+// below 2^29 (larger domains gather every rank).
 // ---------------------------------------------------------------------------
 constexpr int kRecodeHotThreads = 1024;
-constexpr int kRecodeBucketBits = 12;
-constexpr int kRecodeBuckets = 1 << kRecodeBucketBits;  // 4096 buckets x 4 slots, keys + ranks = 128 KB
+constexpr int kRecodeTableWords = 32768;  // 128 KB of LDS
 constexpr int kRecodeHotVecs = 4;
 
-__device__ __forceinline__ uint32_t recode_bucket(uint32_t k) { return (k * 0x9E3779B1u) >> (32 - kRecodeBucketBits); }
+struct TagTable {
+  static constexpr int kBucketBits = 13;
+  static constexpr int kMaxKeys = 3 << kBucketBits;
+  static constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // rank 0xFFFF is never stored
+  uint32_t *slots;  // [4 << kBucketBits]
+  __device__ __forceinline__ TagTable(uint32_t *lds) : slots(lds) {}
+  __device__ __forceinline__ static uint32_t bucket(uint32_t k) { return (k & ((1u << kBucketBits) - 1u)) * 4; }
+  __device__ __forceinline__ void clear() {
+    for (int i = threadIdx.x; i < (4 << kBucketBits); i += blockDim.x) slots[i] = kEmpty;
+  }
+  __device__ __forceinline__ void insert(int32_t k, int32_t r) {
+    const uint32_t b = bucket((uint32_t)k);
+    const uint32_t e = (((uint32_t)k >> kBucketBits) << 16) | (uint32_t)r;
+    for (int j = 0; j < 4; ++j)
+      if (atomicCAS(&slots[b + j], kEmpty, e) == kEmpty) break;
+  }
+  __device__ __forceinline__ bool find(uint32_t uk, int32_t *r) const {
+    const uint32_t tag = uk >> kBucketBits;  // >= 2^16 for keys past 2^29: never equal to a stored tag
+    const uint4 e = *reinterpret_cast<const uint4 *>(slots + bucket(uk));
+    const bool h0 = e.x != kEmpty && (e.x >> 16) == tag, h1 = e.y != kEmpty && (e.y >> 16) == tag;
+    const bool h2 = e.z != kEmpty && (e.z >> 16) == tag, h3 = e.w != kEmpty && (e.w >> 16) == tag;
+    *r = (int32_t)((h0 ? e.x : (h1 ? e.y : (h2 ? e.z : e.w))) & 0xFFFFu);
+    return h0 || h1 || h2 || h3;
+  }
+};
 
-__device__ __forceinline__ int32_t recode_hot_one(const int32_t *tkeys, const int32_t *tranks, rsrc_t ranks,
-                                                  uint32_t n_keys, int32_t k) {
+__device__ __forceinline__ int32_t recode_hot_one(const TagTable &tab, rsrc_t ranks, uint32_t n_keys, int32_t k) {
   const uint32_t uk = (uint32_t)k;
-  const uint32_t b = recode_bucket(uk) * 4;
-  const i32x4 ks = *reinterpret_cast<const i32x4 *>(tkeys + b);
-  const i32x4 rs = *reinterpret_cast<const i32x4 *>(tranks + b);
-  const bool h0 = ks.x == k, h1 = ks.y == k, h2 = ks.z == k, h3 = ks.w == k;
-  const bool hit = h0 || h1 || h2 || h3;
-  const int32_t rl = h0 ? rs.x : (h1 ? rs.y : (h2 ? rs.z : rs.w));
+  int32_t rl;
+  const bool hit = tab.find(uk, &rl);
   const int32_t rg = (int32_t)buffer_load_record(ranks, (int32_t)(hit ? 0xFFFFFFFFu : uk), 0, 0, 0);
   return uk < n_keys ? (hit ? rl : rg) : k;
 }
@@ -304,22 +325,13 @@ __global__ __launch_bounds__(kRecodeHotThreads) void recode_hot_kernel(const int
                                                                        const int32_t *__restrict__ rank,
                                                                        const int32_t *__restrict__ perm,
                                                                        int32_t n_keys, int32_t n_hot, int32_t *out) {
-  __shared__ __align__(16) int32_t tkeys[kRecodeBuckets * 4];
-  __shared__ __align__(16) int32_t tranks[kRecodeBuckets * 4];
-  for (int i = threadIdx.x; i < kRecodeBuckets * 4; i += blockDim.x) tkeys[i] = -1;
+  __shared__ __align__(16) uint32_t lds[kRecodeTableWords];
+  TagTable tab(lds);
+  tab.clear();
   __syncthreads();
   for (int32_t r0 = 0; r0 < n_hot; r0 += kRecodeHotThreads) {  // hottest ranks claim slots first
     const int32_t r = r0 + (int32_t)threadIdx.x;
-    if (r < n_hot) {
-      const int32_t k = perm[r];
-      const uint32_t b = recode_bucket((uint32_t)k) * 4;
-      for (int j = 0; j < 4; ++j) {
-        if (atomicCAS(&tkeys[b + j], -1, k) == -1) {
-          tranks[b + j] = r;
-          break;
-        }
-      }
-    }
+    if (r < n_hot) tab.insert(perm[r], r);
     __syncthreads();
   }
   const rsrc_t rk = record_buffer(rank, (uint32_t)n_keys);
@@ -330,13 +342,13 @@ __global__ __launch_bounds__(kRecodeHotThreads) void recode_hot_kernel(const int
   if ((((uintptr_t)keys ^ (uintptr_t)out) & 15u) != 0) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
-      out[j] = recode_hot_one(tkeys, tranks, rk, nk, keys[j]);
+      out[j] = recode_hot_one(tab, rk, nk, keys[j]);
     return;
   }
-  if (blockIdx.x == 0 && threadIdx.x < sp.head) out[threadIdx.x] = recode_hot_one(tkeys, tranks, rk, nk, keys[threadIdx.x]);
+  if (blockIdx.x == 0 && threadIdx.x < sp.head) out[threadIdx.x] = recode_hot_one(tab, rk, nk, keys[threadIdx.x]);
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x >= kWave && threadIdx.x - kWave < n - sp.tail) {
     const int64_t j = sp.tail + threadIdx.x - kWave;
-    out[j] = recode_hot_one(tkeys, tranks, rk, nk, keys[j]);
+    out[j] = recode_hot_one(tab, rk, nk, keys[j]);
   }
   const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
   i32x4 *vo = reinterpret_cast<i32x4 *>(out + sp.head);
@@ -351,10 +363,10 @@ __global__ __launch_bounds__(kRecodeHotThreads) void recode_hot_kernel(const int
       const int64_t vi = base + u * kRecodeHotThreads + threadIdx.x;
       if (guard && vi >= ve) continue;
       i32x4 y;
-      y.x = recode_hot_one(tkeys, tranks, rk, nk, x[u].x);
-      y.y = recode_hot_one(tkeys, tranks, rk, nk, x[u].y);
-      y.z = recode_hot_one(tkeys, tranks, rk, nk, x[u].z);
-      y.w = recode_hot_one(tkeys, tranks, rk, nk, x[u].w);
+      y.x = recode_hot_one(tab, rk, nk, x[u].x);
+      y.y = recode_hot_one(tab, rk, nk, x[u].y);
+      y.z = recode_hot_one(tab, rk, nk, x[u].z);
+      y.w = recode_hot_one(tab, rk, nk, x[u].w);
       store_stream4(vo + vi, y);
     }
   };
@@ -470,10 +482,10 @@ hipError_t launch_permute_dims(const int32_t *perm, int32_t n, const int32_t *pr
 hipError_t launch_recode(const int32_t *keys, int64_t n, const int32_t *rank, const int32_t *perm, int32_t n_keys,
                          int32_t *out, const DeviceInfo &dev, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (perm && n >= (int64_t)dev.cu_count * 65536) {  // large columns: hot keys through LDS
-    const int32_t n_hot = n_keys < 3 * kRecodeBuckets ? n_keys : 3 * kRecodeBuckets;  // 75 % of the slots
-    hipLaunchKernelGGL(recode_hot_kernel, dim3(dev.cu_count), dim3(kRecodeHotThreads), 0, s, keys, n, rank, perm,
-                       n_keys, n_hot, out);
+  if (perm && n >= (int64_t)dev.cu_count * 65536 && n_keys <= (1 << 29)) {  // large columns: hot keys in LDS
+    const int32_t n_hot = n_keys < TagTable::kMaxKeys ? n_keys : TagTable::kMaxKeys;
+    hipLaunchKernelGGL(recode_hot_kernel, dim3(dev.cu_count), dim3(kRecodeHotThreads), 0, s, keys, n, rank,
+                       perm, n_keys, n_hot, out);
     return hipGetLastError();
   }
   const int64_t need = (n + 4LL * kRecodeThreads - 1) / (4LL * kRecodeThreads);

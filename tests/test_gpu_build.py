@@ -147,3 +147,17 @@ def test_recode_hot_keys(N, s, in_place, offset):
     buf = to_dev(h["fact"])
     L = skew.build_skew_layout(buf[offset:], N, in_place=in_place)
     check(L, ref)
+
+
+def test_recode_hot_keys_colliding_buckets():
+    """Hot keys that all share their low 13 bits fill one bucket of the LDS table; the rest of them are
+    gathered from the rank array, and the recode stays exact."""
+    N, F = 1 << 20, (1 << 24) + 99
+    say("recode hot keys, colliding buckets")
+    rng = np.random.default_rng(13)
+    fact = rng.integers(0, N, F).astype(np.int32)
+    hot = rng.random(F) < 0.5
+    fact[hot] = (rng.integers(0, 64, int(hot.sum())) * 8192).astype(np.int32)
+    ref = oracle.build_layout(fact, N)
+    L = skew.build_skew_layout(to_dev(fact), N)
+    check(L, ref)
