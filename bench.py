@@ -294,7 +294,7 @@ def main():
         result["single_pass"] = {"skew_tuples_per_s": F / (ms_sp * 1e-3), "identity_tuples_per_s": F / (ms_sp_i * 1e-3)}
         del single_ws
     if not args.no_extras:
-        # hot-prefix sweep (rows above the LDS capacity are served from L2: same as the capacity)
+        # hot-prefix sweep, up to the LDS capacity (a larger t is clamped to it)
         cap = skew.max_hot_rows(True)
         sweep_t = []
         for t in (0, 4096, 8192, 16384, 32768, cap):
@@ -320,6 +320,8 @@ def main():
             del d, L
             torch.cuda.empty_cache()
         result["zipf_sweep"] = sweep_s
+    if not args.no_extras:
+        result["small_config"] = bench_small(dev, stream)
     if not args.no_extras or args.with_ops:
         result["operators"] = bench_operators(K, C, price, Cp, pp, perm, N, F, dev, stream)
     if not args.no_extras or args.with_star:
@@ -336,6 +338,44 @@ def main():
         if "bit_exact_vs_oracle" in result["cpu_baseline"]:
             result["bit_exact_vs_oracle"] = result["cpu_baseline"].pop("bit_exact_vs_oracle")
     print(json.dumps(result), flush=True)
+
+
+def bench_small(dev, stream, launches=100, replays=10):
+    """The plain method at small size: a 1e5-row dimension, 1e6 Zipf(1.0) fact keys, SUM(price) and COUNT(*)
+    WHERE category < 4, on both layouts.  Launch-bound, so the query is captured 100 times in one HIP graph and
+    the graph replayed; the per-query time is reported, and the two layouts' answers are compared (the GPU tests
+    check this workload against the oracle)."""
+    import torch
+
+    from paper_1910_10063_amd import skew
+    from paper_1910_10063_amd import workload as W
+
+    k, N, F = 1, 100_000, 1_000_000
+    h = W.host_join_inputs(k, N, F, 1.0)
+    C = torch.from_numpy(h["fact"]).to(dev)
+    price = torch.from_numpy(h["price"]).to(dev)
+    cat = torch.from_numpy(h["category"]).to(dev)
+    L = skew.build_skew_layout(C, N, price, cat)
+    res = {"workload": f"plain method: {N:.0e}-row dimension, {F:.0e} Zipf(1.0) keys, SUM(price), COUNT(*) "
+                       "WHERE category < 4", "queries_per_graph": launches, "graph_replays": replays}
+    for name, keys, pr, ca, t in (("skew", L.fact_recoded, L.price, L.category, skew.SKEW_HOT_AUTO),
+                                  ("identity", C, price, cat, 0)):
+        ws = skew.workspace(skew.SKEW_OP_JOIN, F, N, dev)
+        out = (torch.empty(1, dtype=torch.int64, device=dev), torch.empty(1, dtype=torch.int64, device=dev))
+        skew.fk_join_aggregate(keys, pr, ca, 4, False, hot_rows=t, ws=ws, out=out)  # eager: sets LDS limits
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(launches):
+                skew.fk_join_aggregate(keys, pr, ca, 4, False, hot_rows=t, ws=ws, out=out)
+        ms = timed(g.replay, replays, 1, stream) / launches
+        res[name] = {"us_per_query": round(ms * 1e3, 2), "tuples_per_s": F / (ms * 1e-3),
+                     "sum": int(out[0].cpu()[0]), "count": int(out[1].cpu()[0])}
+        del g, ws
+    res["speedup_vs_identity"] = res["identity"]["us_per_query"] / res["skew"]["us_per_query"]
+    res["layouts_agree"] = (res["skew"]["sum"], res["skew"]["count"]) == (res["identity"]["sum"],
+                                                                         res["identity"]["count"])
+    return res
 
 
 def bench_group_by(K, WU, dev, stream):
