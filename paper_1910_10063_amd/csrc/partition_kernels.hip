@@ -297,8 +297,8 @@ __device__ __forceinline__ int count_bin(uint32_t c) {
   return e * 8 + (int)m;
 }
 
-// Counts [0, n_keys) four at a time (16-byte loads; n_keys is padded to a
-// multiple of 4 by reading the tail one by one).
+// f(k, counts[k]) for every k in [0, n_keys): four counts per 16-byte load,
+// the last n_keys mod 4 one by one.
 template <class F>
 __device__ __forceinline__ void for_each_count(const uint32_t *__restrict__ counts, int32_t n_keys, F f) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
