@@ -632,6 +632,22 @@ def cpu_baseline(C, price, cat, rows, gpu_res):
            "cpu_model": _cpu_model()}
     if gpu_res is not None:
         out["bit_exact_vs_oracle"] = bool((s == gpu_res[0]).all() and (c == gpu_res[1]).all())
+    # the same oracle function on every host core: contiguous chunks of the column, one per thread (the
+    # foreign call releases the interpreter lock), partial sums added in chunk order
+    import concurrent.futures as cf
+
+    cores = min(16, len(os.sched_getaffinity(0)))
+    bounds = np.linspace(0, n, cores + 1).astype(np.int64)
+    t = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        parts = list(ex.map(lambda i: oracle.fk_join_aggregate(Ch[bounds[i]:bounds[i + 1]], ph, ch, 16, True),
+                            range(cores)))
+    dt = time.perf_counter() - t
+    sp = np.sum([p[0] for p in parts], axis=0)
+    cp = np.sum([p[1] for p in parts], axis=0)
+    out["all_cores"] = {"value": n / dt, "unit": "fact tuples/s", "cores": cores, "kind": "oracle",
+                        "sample": f"the same {n} rows in {cores} contiguous chunks, one thread each; {dt:.2f} s",
+                        "equals_one_thread": bool((sp == s).all() and (cp == c).all())}
     return out
 
 
