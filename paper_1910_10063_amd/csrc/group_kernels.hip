@@ -89,12 +89,12 @@ __device__ __forceinline__ void group_one(GroupCtx &c, int32_t g, int32_t v) {
   }
 }
 
-// LDS layout of the range mode: hot_sum[kCopySlots + t + extra] |
-// hot_cnt[kCopySlots + t + extra]; the extra slots are never flushed.
-__device__ __forceinline__ void group_range_init(GroupCtx &c, unsigned char *smem, int32_t t, int32_t extra = 0) {
+// LDS layout of the single pass's range mode: hot_sum[kCopySlots + t] |
+// hot_cnt[kCopySlots + t].
+__device__ __forceinline__ void group_range_init(GroupCtx &c, unsigned char *smem, int32_t t) {
   c.hot_sum = reinterpret_cast<uint64_t *>(smem);
-  c.hot_cnt = reinterpret_cast<uint32_t *>(c.hot_sum + kCopySlots + t + extra);
-  for (int i = threadIdx.x; i < kCopySlots + t + extra; i += blockDim.x) {
+  c.hot_cnt = reinterpret_cast<uint32_t *>(c.hot_sum + kCopySlots + t);
+  for (int i = threadIdx.x; i < kCopySlots + t; i += blockDim.x) {
     c.hot_sum[i] = 0;
     c.hot_cnt[i] = 0;
   }
