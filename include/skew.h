@@ -45,9 +45,10 @@ extern "C" {
  * partitioned by slice and resolved from LDS in a second pass) for inputs of
  * at least 2^22 rows; the *_SINGLE_PASS sizes are the minimum, with which the
  * single-pass kernels run.  A query uses the partitioned form whenever the
- * workspace it is given is large enough for it and its cold ids fit in 1024
- * slices (join: n_rows - t <= 2^25 dimension rows; group-by: n_groups <= 2^23);
- * larger domains run the single pass. */
+ * workspace it is given is large enough for it.  The join partitions at most
+ * 1024 slices (2^25 dimension rows past the hot prefix) and gathers the keys of
+ * any rows beyond them in its first pass; the group-by's partitioned form
+ * needs n_groups <= 2^23 and larger domains run its single pass. */
 #define SKEW_OP_BUILD 1
 #define SKEW_OP_JOIN 2
 #define SKEW_OP_GROUP 3

@@ -245,12 +245,19 @@ __global__ __launch_bounds__(kJoinThreads) void join_kernel(const int32_t *__res
 // key inside the dimension is appended to this workgroup's segment of the
 // cold buffer and counted in its slice ((k - t) >> wshift).  Workgroup b
 // owns a contiguous range of the column, so its segment needs no more slots
-// than the rows it reads.
+// than the rows it reads.  With TAIL, the slices end at tail_start (they are
+// at most kMaxSlices) and keys from there to the end of the dimension, the
+// coldest ones, are gathered from global memory as in the single pass.
 // ---------------------------------------------------------------------------
-template <int GROUPS, int V, bool GUARD>
+struct Tail {
+  uint32_t start;  // first row past the slices (n_rows without a tail)
+  rsrc_t words;    // all dimension words, range-checked
+};
+
+template <int GROUPS, int V, bool GUARD, bool TAIL>
 __device__ __forceinline__ void join_split_batch(JoinCtx<GROUPS> &c, const ColdSink &o, rsrc_t seg,
-                                                 const uint32_t *hot, uint32_t tclamp, const i32x4 (&x)[V],
-                                                 const bool (&valid)[V]) {
+                                                 const uint32_t *hot, uint32_t tclamp, const Tail &tail,
+                                                 const i32x4 (&x)[V], const bool (&valid)[V]) {
   uint32_t k[4 * V], w[4 * V];
   bool cold[4 * V];
 #pragma unroll
@@ -262,10 +269,15 @@ __device__ __forceinline__ void join_split_batch(JoinCtx<GROUPS> &c, const ColdS
   for (int i = 0; i < 4 * V; ++i) {
     const bool ok = !GUARD || valid[i / 4];
     const bool h = ok && k[i] < o.t;
-    cold[i] = ok && !h && k[i] < c.n_rows;
+    cold[i] = ok && !h && k[i] < (TAIL ? tail.start : c.n_rows);
     c.bad |= ok && k[i] >= c.n_rows;
     const uint32_t wl = hot[k[i] < tclamp ? k[i] : tclamp];
     w[i] = h ? wl : kValid;
+    if (TAIL) {  // out-of-range index for every other key: no memory traffic
+      const bool tl = ok && k[i] >= tail.start && k[i] < c.n_rows;
+      const uint32_t wg = buffer_load_record(tail.words, (int32_t)(tl ? k[i] : 0xFFFFFFFFu), 0, 0, 0);
+      w[i] = tl ? wg : w[i];
+    }
   }
   uint32_t all = kValid;
 #pragma unroll
@@ -279,21 +291,24 @@ __device__ __forceinline__ void join_split_batch(JoinCtx<GROUPS> &c, const ColdS
 
 template <int GROUPS>
 __device__ __forceinline__ void join_split_one(JoinCtx<GROUPS> &c, const ColdSink &o, rsrc_t seg,
-                                               const uint32_t *hot, uint32_t tclamp, bool valid, uint32_t k) {
+                                               const uint32_t *hot, uint32_t tclamp, const Tail &tail, bool valid,
+                                               uint32_t k) {
   const bool h = valid && k < o.t;
-  const uint32_t w = h ? hot[k < tclamp ? k : tclamp] : kValid;
+  const bool tl = valid && k >= tail.start && k < c.n_rows;
+  const uint32_t wg = buffer_load_record(tail.words, (int32_t)(tl ? k : 0xFFFFFFFFu), 0, 0, 0);
+  const uint32_t w = h ? hot[k < tclamp ? k : tclamp] : (tl ? wg : kValid);
   c.bad |= valid && k >= c.n_rows;
   join_add(c, w);
   if (!w) join_slow(c, k);
   const uint32_t kk[1] = {k};
-  const bool cd[1] = {valid && !h && k < c.n_rows};
+  const bool cd[1] = {valid && !h && k < tail.start};
   cold_append(o, kk, cd, [&](int, int32_t idx) { buffer_store_record((int32_t)k, seg, idx, 0, 0, 0); });
 }
 
-template <int GROUPS>
+template <int GROUPS, bool TAIL>
 __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
     const int32_t *__restrict__ keys, int64_t n, const uint32_t *__restrict__ words, int32_t n_rows, int32_t t_lds,
-    int32_t P, int32_t wshift, const int32_t *__restrict__ price, const int8_t *__restrict__ cat, int32_t cat_lt,
+    int32_t P, int32_t wshift, int32_t tail_start, const int32_t *__restrict__ price, const int8_t *__restrict__ cat, int32_t cat_lt,
     int64_t *__restrict__ out_sum, int64_t *__restrict__ out_cnt, int32_t *flag, int32_t *__restrict__ cold_seg,
     int64_t seg_cap, uint32_t *__restrict__ seg_count, uint32_t *__restrict__ hist) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -318,6 +333,7 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
   o.wshift = wshift;
   o.sink = (uint32_t)P + lane_id();
   const uint32_t tclamp = t_lds > 0 ? (uint32_t)t_lds - 1 : 0u;
+  const Tail tail{(uint32_t)tail_start, record_buffer(words, (uint32_t)n_rows)};
 
   // Contiguous range of key vectors per workgroup; block 0 takes the scalar
   // head, the last block the scalar tail.
@@ -330,7 +346,7 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
     if (blockIdx.x == 0 && threadIdx.x < sp.head) i = threadIdx.x;
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x >= 64 && threadIdx.x - 64 < n - sp.tail)
       i = sp.tail + threadIdx.x - 64;
-    join_split_one(c, o, seg, hot, tclamp, i >= 0, i >= 0 ? (uint32_t)keys[i] : 0u);
+    join_split_one(c, o, seg, hot, tclamp, tail, i >= 0, i >= 0 ? (uint32_t)keys[i] : 0u);
   }
 
   const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
@@ -348,12 +364,12 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
   while (base < full_end) {
     int64_t nxt = base + tile_vecs;
     load_tile(xb, nxt < full_end ? nxt : base);
-    join_split_batch<GROUPS, kJoinVecs, false>(c, o, seg, hot, tclamp, xa, all_valid);
+    join_split_batch<GROUPS, kJoinVecs, false, TAIL>(c, o, seg, hot, tclamp, tail, xa, all_valid);
     base = nxt;
     if (base >= full_end) break;
     nxt = base + tile_vecs;
     load_tile(xa, nxt < full_end ? nxt : base);
-    join_split_batch<GROUPS, kJoinVecs, false>(c, o, seg, hot, tclamp, xb, all_valid);
+    join_split_batch<GROUPS, kJoinVecs, false, TAIL>(c, o, seg, hot, tclamp, tail, xb, all_valid);
     base = nxt;
   }
   if (full_end < ve) {  // last partial tile
@@ -365,7 +381,7 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
       valid[u] = vi < ve;
       x[u] = valid[u] ? load_stream4(vk + vi) : i32x4{0, 0, 0, 0};
     }
-    join_split_batch<GROUPS, kJoinVecs, true>(c, o, seg, hot, tclamp, x, valid);
+    join_split_batch<GROUPS, kJoinVecs, true, TAIL>(c, o, seg, hot, tclamp, tail, x, valid);
   }
   __syncthreads();
   if (threadIdx.x == 0) seg_count[blockIdx.x] = *lcount < seg_cap ? *lcount : (uint32_t)seg_cap;
@@ -519,6 +535,7 @@ JoinPlan join_plan(int64_t n_fact, int32_t n_rows, int32_t t, int groups, const 
   pl.wshift = kJoinSliceShift;
   const int64_t cold_rows = (int64_t)n_rows - t;
   pl.slices = cold_rows > 0 ? (int32_t)((cold_rows + (1 << pl.wshift) - 1) >> pl.wshift) : 0;
+  if (pl.slices > kMaxSlices) pl.slices = kMaxSlices;  // rows past the last slice are gathered (the tail)
   pl.round = n_fact < kJoinMaxRound ? n_fact : kJoinMaxRound;
   const int64_t nvec = (pl.round + 3) / 4 + 1;
   pl.seg_cap = 4 * ((nvec + pl.blocks - 1) / pl.blocks) + 8;
@@ -553,7 +570,7 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
   if (t < 0) t = 0;
 
   const JoinPlan pl = join_plan(n_fact, n_rows, t, groups, dev);
-  const bool partitioned = part_ws && n_fact >= kPartitionMinFact && pl.slices > 0 && pl.slices <= kMaxSlices &&
+  const bool partitioned = part_ws && n_fact >= kPartitionMinFact && pl.slices > 0 &&
                            part_bytes >= join_partition_bytes(pl);
   if (!partitioned) {
     const size_t lds = join_lds_bytes(groups, t);
@@ -601,24 +618,21 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
   const size_t lds1 = join_lds_bytes(groups, t) + (size_t)(pl.slices + kWave + 4) * 4;
   const size_t lds3 = (groups == 16 ? (size_t)kJoinBins * kWave * 8 : 0) + ((size_t)4 << pl.wshift) +
                       (size_t)(pl.slices + 1) * 4;
-  if (groups == 16) {
-    allow_lds(join_split_kernel<16>, lds1);
-    allow_lds(join_slice_kernel<16>, lds3);
-  } else {
-    allow_lds(join_split_kernel<1>, lds1);
-    allow_lds(join_slice_kernel<1>, lds3);
-  }
+  // keys past the last slice (dimensions of more than kMaxSlices slices) are gathered in pass 1
+  const int64_t tail_row = (int64_t)t + ((int64_t)pl.slices << pl.wshift);
+  const int32_t tail_start = tail_row < n_rows ? (int32_t)tail_row : n_rows;
+  const bool tail = tail_start < n_rows;
+  auto split_kernel = groups == 16 ? (tail ? join_split_kernel<16, true> : join_split_kernel<16, false>)
+                                   : (tail ? join_split_kernel<1, true> : join_split_kernel<1, false>);
+  allow_lds(split_kernel, lds1);
+  if (groups == 16) allow_lds(join_slice_kernel<16>, lds3);
+  else allow_lds(join_slice_kernel<1>, lds3);
   for (int64_t off = 0; off < n_fact; off += pl.round) {
     const int64_t n = n_fact - off < pl.round ? n_fact - off : pl.round;
     st = stage_begin("join_split", s);
-    if (groups == 16)
-      hipLaunchKernelGGL(join_split_kernel<16>, dim3(pl.blocks), dim3(kJoinThreads), lds1, s, keys + off, n, words,
-                         n_rows, t, pl.slices, pl.wshift, price, cat, cat_lt, out_sum, out_cnt, flag, seg, pl.seg_cap,
-                         tab.seg_count, tab.hist);
-    else
-      hipLaunchKernelGGL(join_split_kernel<1>, dim3(pl.blocks), dim3(kJoinThreads), lds1, s, keys + off, n, words,
-                         n_rows, t, pl.slices, pl.wshift, price, cat, cat_lt, out_sum, out_cnt, flag, seg, pl.seg_cap,
-                         tab.seg_count, tab.hist);
+    hipLaunchKernelGGL(split_kernel, dim3(pl.blocks), dim3(kJoinThreads), lds1, s, keys + off, n, words, n_rows, t,
+                       pl.slices, pl.wshift, tail_start, price, cat, cat_lt, out_sum, out_cnt, flag, seg, pl.seg_cap,
+                       tab.seg_count, tab.hist);
     e = hipGetLastError();
     stage_end(st, s);
     st = stage_begin("join_plan", s);

@@ -369,3 +369,27 @@ def test_generator_device_matches_host():
         assert (host(part) == W.fact_keys(77, cdf, pi, 1000, start=123_456)).all()
     v = W.device_uniform_i32(5, 0, 1000, 100_003, DEV)
     assert (host(v) == W.uniform_int(5, 0, 1000, 100_003)).all()
+
+
+def test_partitioned_join_with_gathered_tail():
+    """A dimension larger than the slices can cover (1024 slices of 32768 rows past the hot prefix): keys past the
+    last slice are gathered in pass 1, the rest partitioned; escapes and odd categories in both parts."""
+    say("partitioned join with a gathered tail")
+    rng = np.random.default_rng(77)
+    N, F = 40_000_000, (1 << 22) + 12_345
+    h = W.host_join_inputs(14, N, F, 0.7)
+    price, cat = h["price"].copy(), h["category"].copy()
+    tail_rows = rng.integers(34_000_000, N, 2000)
+    price[tail_rows[:1000]] = rng.integers(1 << 25, 2**31 - 1, 1000)  # escapes in the tail
+    cat[tail_rows[1000:]] = -5
+    price[rng.integers(0, 1_000_000, 500)] = -3                          # escapes in the slices
+    fact = h["fact"]
+    assert (fact >= 34_000_000).sum() > 10_000, "the column must reach the tail"
+    ws = skew.workspace(skew.SKEW_OP_JOIN, F, N, DEV)
+    fd, pd, cd = to_dev(fact), to_dev(price), to_dev(cat)
+    for by_cat, cat_lt in ((True, 16), (False, 9)):
+        es, ec = oracle.fk_join_aggregate(fact, price, cat, cat_lt, by_cat)
+        for t in (0, 7, skew.SKEW_HOT_AUTO):
+            s, c = skew.fk_join_aggregate(fd, pd, cd, cat_lt, by_cat, hot_rows=t, ws=ws)
+            assert (host(s) == es).all() and (host(c) == ec).all(), (by_cat, t)
+    assert skew.query_status(ws) == skew.SKEW_OK
