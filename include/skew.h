@@ -266,12 +266,15 @@ int cache_model_hit_rate(const uint32_t *counts_by_rank, int32_t n_keys, const i
  *
  * One persistent kernel takes tiles of tile_rows rows from a device work queue
  * (a tile never spans two queries), so queries of very different sizes share
- * the GPU.  Every launch of the call is a kernel, so a caller may capture the
- * call in a HIP graph and replay it.
+ * the GPU.  Before it, a kernel evaluates every query's filter on the hot
+ * customer rows into a per-query bitmap in the workspace; a workgroup stages
+ * the bitmap of the query it works on into LDS.  Every launch of the call is
+ * a kernel, so a caller may capture the call in a HIP graph and replay it.
  */
 typedef struct {
   int32_t prod_hot_rows; /* product rows [0, t) read from LDS (clamped to capacity) */
-  int32_t cust_hot_rows; /* customer rows [0, t) read from LDS (1 byte each) */
+  int32_t cust_hot_rows; /* customer rows [0, t) resolved from LDS, t <= 2^20: one bit
+                            per row, the outcome of the query's filter */
   int32_t tile_rows;     /* rows per work-queue tile, in [1024, 2^24] */
   int32_t blocks;        /* persistent workgroups; 0 = one per compute unit */
 } skew_star_tuning;
@@ -288,7 +291,10 @@ typedef struct {
  *   tuning                      host pointer; NULL = defaults (see star_join_autotune).
  *   out_sum, out_count          int64[n_queries * 16] (query-major).
  *   workspace                   >= skew_workspace_bytes(SKEW_OP_STAR, n_queries,
- *                               max(n_prod, n_cust)).
+ *                               max(n_prod, n_cust)): packed product words
+ *                               (4 bytes per row), a padded copy of the
+ *                               segments, the work queue, and one bitmap of
+ *                               min(n_cust, 2^20) bits per query.
  * Keys outside their dimension join nothing and set the error flag.
  */
 int star_join_batch(const int32_t *prod_keys, const int32_t *cust_keys, const int64_t *query_start,

@@ -112,7 +112,9 @@ hipError_t launch_cache_model(const uint32_t *counts_by_rank, int32_t n_keys, co
 
 // ---- batched star join ----
 constexpr int32_t kMaxStarQueries = 4096;
+constexpr int32_t kStarMaxCustHot = 1 << 20;  // customer bitmap rows per query (128 KB)
 size_t star_lds_bytes(int32_t tp, int32_t tc, int32_t nq);
+int32_t star_bits_stride(int32_t tc);
 int32_t star_max_prod_hot(int32_t tc, int32_t nq, const DeviceInfo &dev);
 int32_t star_max_cust_hot(int32_t nq, const DeviceInfo &dev);
 size_t star_workspace_bytes(int32_t n_prod, int32_t n_cust, int32_t nq);

@@ -511,12 +511,12 @@ int star_check(const int32_t *prod_keys, const int32_t *cust_keys, const int64_t
 skew_star_tuning star_resolve(const skew_star_tuning *t, int32_t n_prod, int32_t n_cust, int32_t nq,
                               const skew::DeviceInfo &dev) {
   skew_star_tuning r;
-  r.cust_hot_rows = t ? t->cust_hot_rows : 16384;
+  r.cust_hot_rows = t ? t->cust_hot_rows : 262144;
   r.tile_rows = t ? t->tile_rows : 262144;
   r.blocks = t && t->blocks > 0 ? t->blocks : dev.cu_count;
   if (r.cust_hot_rows < 0) r.cust_hot_rows = 0;
   if (r.cust_hot_rows > n_cust) r.cust_hot_rows = n_cust;
-  int32_t cmax = 131072 < n_cust ? 131072 : n_cust;  // keep some LDS for the product prefix
+  int32_t cmax = skew::kStarMaxCustHot < n_cust ? skew::kStarMaxCustHot : n_cust;
   const int32_t cfit = skew::star_max_cust_hot(nq, dev);
   if (cmax > cfit) cmax = cfit;
   if (r.cust_hot_rows > cmax) r.cust_hot_rows = cmax;
@@ -569,7 +569,7 @@ int star_join_autotune(const int32_t *prod_keys, const int32_t *cust_keys, const
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
   if (e != hipSuccess) return hip_fail(e, "autotune events");
-  const int32_t cust_cand[] = {0, 8192, 32768, 65536, 98304, 131072};
+  const int32_t cust_cand[] = {0, 65536, 262144, 524288, 786432, 1048576};
   const int32_t tile_cand[] = {65536, 262144, 1048576};
   float best_t = -1.f;
   skew_star_tuning arg{-1, 0, 0, 0};

@@ -4,9 +4,13 @@
 // Workgroups take tiles of rows from a device work queue; a tile never spans
 // two queries.  Both dimensions keep their hot prefix in LDS (Section 4.2:
 // on the frequency-ordered layouts the hot rows are the first ones) and the
-// rest is gathered through range-checked buffer loads.  Every launch here is
-// a kernel (no memset or host copy), so the whole call can be captured in a
-// HIP graph and replayed.
+// rest is gathered through range-checked buffer loads.  The product prefix is
+// one packed word per row, shared by all queries.  The customer prefix is the
+// filter's outcome, one bit per row, so a workgroup holds eight times more
+// hot customers than it would segments; every query has its own bitmap,
+// built before the batch kernel and staged into LDS when a workgroup moves on
+// to a tile of another query.  Every launch here is a kernel (no memset or
+// host copy), so the whole call can be captured in a HIP graph and replayed.
 #include "kernels.h"
 #include "profiler.h"
 #include "query_common.h"
@@ -16,7 +20,12 @@ namespace {
 
 constexpr int kStarThreads = 1024;
 constexpr int kStarVecs = 2;       // 16-byte vectors of each key column per lane per batch
-constexpr int kStarBins = kJoinBins;
+// Bins 1..16 are the groups and bin 0 the sink: every word the kernel adds is
+// a packed product word (group field category + 1 <= 16), kValid (field 0) or
+// 0, so the 5-bit group field never exceeds 16.
+constexpr int kStarBins = 17;
+constexpr int kBitsThreads = 256;
+constexpr int kBitsQueries = 8;    // queries per workgroup of the bitmap kernel
 
 // Product word: kValid | (category + 1) << 25 | price, kValid alone for a row
 // outside every group, 0 when the price does not fit (slow path).
@@ -32,8 +41,31 @@ __global__ void star_pack_kernel(const int32_t *__restrict__ price, const int8_t
     if (c >= 0 && c < 16) w = ((uint32_t)p <= kPriceMask) ? (kValid | ((uint32_t)(c + 1) << kGroupShift) | (uint32_t)p) : 0u;
     words[r] = w;
   }
-  // customer segments, padded to whole words with a value no threshold admits
+  // customer segments, padded to whole 32-row groups (the padding rows are
+  // past the dimension and never pass: every lookup checks the row first)
   for (int64_t r = gid; r < attr_padded; r += stride) attr_copy[r] = r < n_cust ? attr[r] : (int8_t)127;
+}
+
+// Customer bitmaps of the hot prefix: bit u of query q's bitmap (word u / 32,
+// bit u % 32) is set when segment[u] < threshold[q], for rows [0, tc).  One
+// thread reads the 32 segments of one word once and writes that word for
+// kBitsQueries queries; the bitmaps are `stride` words apart.
+__global__ __launch_bounds__(kBitsThreads) void star_bits_kernel(const uint4 *__restrict__ segs, int32_t n_words,
+                                                                 const int32_t *__restrict__ qlt, int32_t nq,
+                                                                 int32_t stride, uint32_t *__restrict__ bits) {
+  const int32_t w = blockIdx.x * kBitsThreads + threadIdx.x;
+  if (w >= n_words) return;
+  const uint4 a = segs[2 * w], b = segs[2 * w + 1];  // rows 32w .. 32w + 31
+  const uint32_t sw[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  const int32_t q0 = blockIdx.y * kBitsQueries;
+  const int32_t q1 = q0 + kBitsQueries < nq ? q0 + kBitsQueries : nq;
+  for (int32_t q = q0; q < q1; ++q) {
+    const int32_t lt = qlt[q];
+    uint32_t word = 0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) word |= (uint32_t)((int32_t)(int8_t)(sw[i >> 2] >> (8 * (i & 3))) < lt) << i;
+    bits[(int64_t)q * stride + w] = word;
+  }
 }
 
 // Tile table: tiles of query q start at tile_start[q]; outputs and the queue
@@ -83,20 +115,23 @@ struct StarCtx {
   const uint32_t *phot;  // LDS: product words [0, tp)
   uint32_t tp, tpclamp;
   rsrc_t pwords;         // all product words (range-checked)
-  const uint32_t *chot;  // LDS: customer segments [0, tc) as words
-  uint32_t tc, tcclamp;  // in rows (bytes)
-  rsrc_t cwords;         // all customer segments as words (range-checked)
+  const uint32_t *chot;  // LDS: the current query's customer bitmap, rows [0, tc)
+  uint32_t tc, tcclamp;  // tc in rows (bits), tcclamp in words
+  rsrc_t cwords;         // all customer segments, four to a word (range-checked)
   uint32_t n_prod, n_cust;
 };
 
-// Customer segment of row u (0 outside the dimension: checked separately).
-__device__ __forceinline__ int32_t cust_segment(const StarCtx &x, uint32_t u) {
+// Whether customer row u < n_cust passes the query's filter: a bit of the
+// LDS bitmap for a hot row, the row's segment gathered and compared for a
+// cold one (the gather index is pushed out of range for hot rows, so they
+// cost no memory traffic).
+__device__ __forceinline__ bool cust_pass(const StarCtx &x, uint32_t u, int32_t lt) {
   const bool hot = u < x.tc;
-  const uint32_t wi = u >> 2;
-  const uint32_t wl = x.chot[wi < x.tcclamp ? wi : x.tcclamp];
-  const uint32_t wg = buffer_load_record(x.cwords, (int32_t)(hot ? 0xFFFFFFFFu : wi), 0, 0, 0);
-  const uint32_t w = hot ? wl : wg;
-  return (int32_t)(int8_t)(w >> (8 * (u & 3u)));
+  const uint32_t wi = u >> 5;
+  const uint32_t bl = x.chot[wi < x.tcclamp ? wi : x.tcclamp] >> (u & 31u);
+  const uint32_t wg = buffer_load_record(x.cwords, (int32_t)(hot ? 0xFFFFFFFFu : (u >> 2)), 0, 0, 0);
+  const int32_t seg = (int32_t)(int8_t)(wg >> (8 * (u & 3u)));
+  return hot ? (bl & 1u) != 0u : seg < lt;
 }
 
 // Product word of row p for a row whose customer passed; for the other rows
@@ -118,7 +153,7 @@ struct StarAcc {
 };
 
 __device__ __forceinline__ void star_add(StarAcc &a, uint32_t w) {
-  const uint32_t bin = (w >> kGroupShift) & (kStarBins - 1);
+  const uint32_t bin = (w >> kGroupShift) & (kJoinBins - 1);
   lds_add_u64(&a.bins[bin * kWave + lane_id()], (1ull << kCountShift) | (w & kPriceMask));
 }
 
@@ -137,7 +172,7 @@ __device__ __forceinline__ void star_slow(StarAcc &a, const StarCtx &x, uint32_t
 
 // One row: product word if the customer passes, the sink bin otherwise.
 __device__ __forceinline__ void star_row(StarAcc &a, const StarCtx &x, uint32_t p, uint32_t u, int32_t lt) {
-  const bool pass = u < x.n_cust && cust_segment(x, u) < lt;
+  const bool pass = u < x.n_cust && cust_pass(x, u, lt);
   const uint32_t wp = prod_word(x, p, pass);
   const uint32_t w = pass ? wp : kValid;
   star_add(a, w);
@@ -171,20 +206,20 @@ __global__ __launch_bounds__(kStarThreads) void star_batch_kernel(
     const int32_t *__restrict__ qlt, int32_t nq, const uint32_t *__restrict__ tile_start, uint32_t *counter,
     int64_t tile_rows, const uint32_t *__restrict__ pwords, int32_t n_prod, int32_t tp,
     const uint32_t *__restrict__ cwords, int32_t n_cust, int32_t tc, const int32_t *__restrict__ price,
-    const int8_t *__restrict__ cat, int64_t *__restrict__ out_sum, int64_t *__restrict__ out_cnt, int32_t *flag) {
+    const int8_t *__restrict__ cat, const uint32_t *__restrict__ cbits, int32_t cstride,
+    int64_t *__restrict__ out_sum, int64_t *__restrict__ out_cnt, int32_t *flag) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_tile;
   uint64_t *bins = reinterpret_cast<uint64_t *>(smem);
   uint32_t *phot = reinterpret_cast<uint32_t *>(smem + kStarBins * kWave * 8);
   const int32_t tp_words = (tp + 4) & ~3;
   uint32_t *chot = phot + tp_words;
-  const int32_t tc_words = ((tc + 3) / 4 + 4) & ~3;
-  uint32_t *lts = chot + tc_words;                 // [nq + 1] tile starts
+  const int32_t tc_bits_words = (tc + 31) / 32;
+  uint32_t *lts = chot + ((tc_bits_words + 4) & ~3);  // [nq + 1] tile starts
   for (int i = threadIdx.x; i < kStarBins * kWave; i += blockDim.x) bins[i] = 0;
   stage_words(phot, pwords, 0, tp);
   if (tp == 0 && threadIdx.x == 0) phot[0] = 0;
-  stage_words(chot, cwords, 0, (tc + 3) / 4);
-  if (tc == 0 && threadIdx.x == 0) chot[0] = 0;
+  if (threadIdx.x == 0) chot[0] = 0;  // read (clamped) when tc == 0
   for (int q = threadIdx.x; q <= nq; q += blockDim.x) lts[q] = tile_start[q];
   __syncthreads();
 
@@ -195,7 +230,7 @@ __global__ __launch_bounds__(kStarThreads) void star_batch_kernel(
   x.pwords = record_buffer(pwords, (uint32_t)n_prod);
   x.chot = chot;
   x.tc = (uint32_t)tc;
-  x.tcclamp = tc > 0 ? (uint32_t)((tc + 3) / 4) - 1 : 0u;
+  x.tcclamp = tc > 0 ? (uint32_t)tc_bits_words - 1 : 0u;
   x.cwords = record_buffer(cwords, (uint32_t)((n_cust + 3) / 4));
   x.n_prod = (uint32_t)n_prod;
   x.n_cust = (uint32_t)n_cust;
@@ -207,6 +242,7 @@ __global__ __launch_bounds__(kStarThreads) void star_batch_kernel(
   const uint32_t total = lts[nq];
   const i32x4 *vp = reinterpret_cast<const i32x4 *>(pkeys);
   const i32x4 *vu = reinterpret_cast<const i32x4 *>(ukeys);
+  int32_t staged_q = -1;  // query whose bitmap is in LDS
 
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
@@ -221,6 +257,11 @@ __global__ __launch_bounds__(kStarThreads) void star_batch_kernel(
       else hi_q = m - 1;
     }
     const int32_t q = lo_q;
+    if (q != staged_q && tc > 0) {  // uniform: every thread has the same tile; the last tile's reads are done
+      stage_words(chot, cbits, (int64_t)q * cstride, tc_bits_words);
+      __syncthreads();
+      staged_q = q;
+    }
     const int64_t r0 = qstart[q] + (int64_t)(tile - lts[q]) * tile_rows;
     const int64_t r1 = r0 + tile_rows < qstart[q + 1] ? r0 + tile_rows : qstart[q + 1];
     const int32_t lt = qlt[q];
@@ -250,7 +291,7 @@ __global__ __launch_bounds__(kStarThreads) void star_batch_kernel(
 #pragma unroll
           for (int i = 0; i < 4 * kStarVecs; ++i) {
             const bool in_c = u[i] < x.n_cust;
-            pass[i] = valid[i / 4] && in_c && cust_segment(x, u[i]) < lt;
+            pass[i] = valid[i / 4] && in_c && cust_pass(x, u[i], lt);
             const uint32_t wp = prod_word(x, p[i], pass[i]);
             w[i] = pass[i] ? wp : kValid;
             rare |= (uint32_t)((pass[i] && wp == 0u) || (valid[i / 4] && (!in_c || p[i] >= x.n_prod)));
@@ -291,9 +332,11 @@ constexpr size_t kStaticReserve = 512;
 }  // namespace
 
 size_t star_lds_bytes(int32_t tp, int32_t tc, int32_t nq) {
-  return (size_t)kStarBins * kWave * 8 + (size_t)((tp + 4) & ~3) * 4 + (size_t)((((tc + 3) / 4) + 4) & ~3) * 4 +
+  return (size_t)kStarBins * kWave * 8 + (size_t)((tp + 4) & ~3) * 4 + (size_t)((((tc + 31) / 32) + 4) & ~3) * 4 +
          (size_t)(nq + 1) * 4;
 }
+
+int32_t star_bits_stride(int32_t tc) { return (((tc + 31) / 32) + 3) & ~3; }
 
 int32_t star_max_prod_hot(int32_t tc, int32_t nq, const DeviceInfo &dev) {
   const size_t fixed = star_lds_bytes(0, tc, nq) - 16 + kStaticReserve;
@@ -305,12 +348,21 @@ int32_t star_max_cust_hot(int32_t nq, const DeviceInfo &dev) {
   // with an empty product prefix: bins, query table, reserve, and 16 bytes of padding per table
   const size_t fixed = star_lds_bytes(0, 0, nq) + 16 + kStaticReserve;
   if (dev.lds_per_block <= fixed) return 0;
-  return (int32_t)(((dev.lds_per_block - fixed) / 16) * 16);  // whole words of 4 one-byte entries
+  const size_t rows = ((dev.lds_per_block - fixed) / 16) * 128;  // whole 16-byte vectors of bits
+  return (int32_t)(rows < (size_t)kStarMaxCustHot ? rows : (size_t)kStarMaxCustHot);
 }
+
+namespace {
+size_t seg_padded(int32_t n_cust) { return ((size_t)n_cust + 31) / 32 * 32; }
+size_t star_bits_words(int32_t n_cust) {
+  return (size_t)star_bits_stride(n_cust < kStarMaxCustHot ? n_cust : kStarMaxCustHot);
+}
+}  // namespace
 
 size_t star_workspace_bytes(int32_t n_prod, int32_t n_cust, int32_t nq) {
   auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  return r((size_t)n_prod * 4) + r(((size_t)n_cust + 3) / 4 * 4 + 16) + r((size_t)(nq + 1) * 4) + r(16);
+  return r((size_t)n_prod * 4) + r(seg_padded(n_cust) + 16) + r((size_t)(nq + 1) * 4) + r(16) +
+         r((size_t)nq * star_bits_words(n_cust) * 4);
 }
 
 hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t *qstart, const int32_t *qlt,
@@ -322,11 +374,15 @@ hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t
   uint32_t *pwords = (uint32_t *)w;
   w += r((size_t)n_prod * 4);
   int8_t *cwords = (int8_t *)w;
-  const int32_t attr_padded = (int32_t)(((int64_t)n_cust + 3) / 4 * 4);
+  const int32_t attr_padded = (int32_t)seg_padded(n_cust);
   w += r((size_t)attr_padded + 16);
   uint32_t *tile_start = (uint32_t *)w;
   w += r((size_t)(nq + 1) * 4);
   uint32_t *counter = (uint32_t *)w;
+  w += r(16);
+  uint32_t *cbits = (uint32_t *)w;  // nq bitmaps of cstride words (16-byte aligned)
+  const int32_t cstride = star_bits_stride(tc);
+  if (tc < 0 || tc > n_cust || tc > kStarMaxCustHot) return hipErrorInvalidValue;
 
   StageTimer st = stage_begin("star_prep", s);
   const int64_t n_pack = n_prod > attr_padded ? n_prod : attr_padded;
@@ -335,6 +391,13 @@ hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t
   hipLaunchKernelGGL(star_pack_kernel, dim3((int)(g > 0 ? g : 1)), dim3(256), 0, s, price, cat, n_prod, pwords, attr,
                      n_cust, cwords, attr_padded);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && tc > 0) {
+    const int32_t n_words = (tc + 31) / 32;
+    const dim3 grid((n_words + kBitsThreads - 1) / kBitsThreads, (nq + kBitsQueries - 1) / kBitsQueries);
+    hipLaunchKernelGGL(star_bits_kernel, grid, dim3(kBitsThreads), 0, s, reinterpret_cast<const uint4 *>(cwords),
+                       n_words, qlt, nq, cstride, cbits);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(star_plan_kernel, dim3(1), dim3(1024), 0, s, qstart, nq, tile_rows, tile_start, counter,
                        out_sum, out_cnt, flag);
@@ -347,7 +410,7 @@ hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t
   st = stage_begin("star_batch", s);
   hipLaunchKernelGGL(star_batch_kernel, dim3(blocks), dim3(kStarThreads), lds, s, pkeys, ukeys, qstart, qlt, nq,
                      tile_start, counter, tile_rows, pwords, n_prod, tp, (const uint32_t *)cwords, n_cust, tc, price,
-                     cat, out_sum, out_cnt, flag);
+                     cat, cbits, cstride, out_sum, out_cnt, flag);
   e = hipGetLastError();
   stage_end(st, s);
   return e;

@@ -76,7 +76,7 @@ def test_star_batch(batch, tun, layout):
 
 @pytest.fixture(scope="module")
 def wide():
-    """A customer dimension larger than the biggest LDS customer prefix (131072 rows)."""
+    """A customer dimension larger than the default LDS customer prefix (262144 rows)."""
     k, n_prod, n_cust = 5, 200_000, 300_000
     sizes = np.array([70_001, 1_000_003, 5], dtype=np.int64)
     say(f"star wide batch n_prod={n_prod} n_cust={n_cust}")
@@ -105,8 +105,45 @@ def test_star_wide_customer_prefix(wide, tun, layout):
 def test_star_autotune_wide(wide):
     say("star autotune wide")
     best, ms = skew.star_join_autotune(wide["skew"])
-    assert ms > 0 and best.cust_hot_rows <= 131_072
+    assert ms > 0 and best.cust_hot_rows <= 300_000
     check(skew.star_join_batch(wide["skew"], best), wide["want"])
+
+
+@pytest.fixture(scope="module")
+def signed():
+    """1.2M customers (more than the largest LDS bitmap, 2^20 rows) with segments in [-100, 98] and thresholds
+    at and around the ends of the int8 range; six queries, so workgroups move between queries' bitmaps."""
+    k, n_prod, n_cust = 6, 150_000, 1_200_000
+    sizes = np.array([70_001, 900_007, 5, 0, 200_000, 31], dtype=np.int64)
+    say(f"star signed batch n_prod={n_prod} n_cust={n_cust}")
+    h = W.host_star_inputs(k, n_prod, n_cust, sizes)
+    seg = (h["cust_attr"].astype(np.int16) * 2 - 100).astype(np.int8)
+    lt = np.array([-50, 17, 127, 0, -128, 128], dtype=np.int32)
+    start = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    want = [oracle.star_join(h["prod"][a:b], h["cust"][a:b], h["price"], h["category"], seg, lt[q])
+            for q, (a, b) in enumerate(zip(start[:-1], start[1:]))]
+    ident = skew.StarBatch(to_dev(h["prod"]), to_dev(h["cust"]), to_dev(start), to_dev(lt), to_dev(h["price"]),
+                           to_dev(h["category"]), to_dev(seg))
+    Lp = skew.build_skew_layout(ident.prod_keys, n_prod, ident.price, ident.category)
+    Lc = skew.build_skew_layout(ident.cust_keys, n_cust, None, ident.segment)
+    sk = skew.StarBatch(Lp.fact_recoded, Lc.fact_recoded, ident.query_start, ident.query_cust_lt, Lp.price,
+                        Lp.category, Lc.category)
+    return dict(identity=ident, skew=sk, want=want)
+
+
+@pytest.mark.parametrize("tun", [None, (-1, 1 << 20, 262_144, 0), (-1, 1_000_001, 4096, 0), (7, 524_295, 65_536, 9),
+                                 (-1, 31, 1024, 0), (0, 0, 262_144, 0)], ids=str)
+@pytest.mark.parametrize("layout", ["skew", "identity"])
+def test_star_signed_segments_large_prefix(signed, tun, layout):
+    say(f"star signed {layout} tuning={tun}")
+    check(skew.star_join_batch(signed[layout], None if tun is None else skew.StarTuning(*tun)), signed["want"])
+
+
+def test_star_autotune_signed(signed):
+    say("star autotune signed")
+    best, ms = skew.star_join_autotune(signed["skew"])
+    assert ms > 0 and 0 <= best.cust_hot_rows <= 1 << 20
+    check(skew.star_join_batch(signed["skew"], best), signed["want"])
 
 
 def test_star_autotune(batch):
