@@ -61,7 +61,8 @@ extern "C" {
 #define SKEW_OP_STAR 10       /* star_join_batch: n_fact = queries, n_keys = max(n_prod, n_cust) */
 
 /* hot_rows / hot_groups special values. */
-#define SKEW_HOT_AUTO (-1)  /* library picks the hot prefix from LDS capacity */
+#define SKEW_HOT_AUTO (-1)  /* library picks the hot prefix: LDS capacity (the join
+                               * takes less in its single pass on small inputs) */
 #define SKEW_HOT_NONE (-2)  /* group_aggregate only: global atomics for every row */
 
 /* Message of the last failed call on this thread ("" if none); valid until the

@@ -32,6 +32,7 @@ __global__ void join_pack_kernel(const int32_t *__restrict__ price, const int8_t
 }
 
 constexpr int kJoinVecs = 4;  // 16-byte key vectors per lane per batch
+constexpr int64_t kJoinAutoMinHot = 8192;  // smallest automatic prefix of the single pass
 
 // Accumulators.  GROUPS == 16: every lane owns one 64-bit bin per group in
 // LDS, shared by the 16 waves of the workgroup through LDS atomics (two lanes
@@ -563,11 +564,11 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
   hipError_t e = hipGetLastError();
   stage_end(st, s);
   if (e != hipSuccess || n_fact == 0) return e;
+  const bool auto_t = hot_rows < 0;  // SKEW_HOT_AUTO
   int32_t t = hot_rows;
   const int32_t cap = join_max_hot_rows(groups, dev);
-  if (t > cap) t = cap;
+  if (auto_t || t > cap) t = cap;
   if (t > n_rows) t = n_rows;
-  if (t < 0) t = 0;
 
   const JoinPlan pl = join_plan(n_fact, n_rows, t, groups, dev);
   const bool partitioned = part_ws && n_fact >= kPartitionMinFact && pl.slices > 0 &&
@@ -577,6 +578,15 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
     // Every lane's bins must see fewer than 2^19 rows per launch: at most 16
     // waves share a bin, so a thread handles at most 2^14 rows per launch.
     const int64_t per_launch_max = (int64_t)dev.cu_count * kJoinThreads * (1LL << 14);
+    if (auto_t) {
+      // Every workgroup copies the prefix into LDS: for a small input, a prefix much longer than half the
+      // keys a workgroup reads costs more to stage than its lookups save (8192 rows at 1e6-4e6 keys).
+      const int64_t n0 = n_fact < per_launch_max ? n_fact : per_launch_max;
+      const int64_t need = (n0 + 4LL * kJoinThreads - 1) / (4LL * kJoinThreads);
+      const int64_t per_wg = n0 / (need < dev.cu_count ? need : dev.cu_count);
+      const int64_t ta = per_wg / 2 > kJoinAutoMinHot ? per_wg / 2 : kJoinAutoMinHot;
+      if (ta < t) t = (int32_t)ta;
+    }
     if (groups == 16) allow_lds(join_kernel<16>, lds);
     else allow_lds(join_kernel<1>, lds);
     for (int64_t off = 0; off < n_fact; off += per_launch_max) {

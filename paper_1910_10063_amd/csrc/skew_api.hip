@@ -315,12 +315,11 @@ int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *d
   skew::DeviceInfo dev;
   if (int rc = device_info(&dev)) return rc;
   const int groups = group_by_category ? 16 : 1;
-  const int32_t t = hot_rows == SKEW_HOT_AUTO ? skew::join_max_hot_rows(groups, dev) : hot_rows;
   const hipStream_t s = (hipStream_t)stream;
   char *ws = (char *)workspace;
   void *part = workspace_bytes > need ? (void *)(ws + need) : nullptr;
   const hipError_t e = skew::launch_join(fact_keys, n_fact, dim_price, dim_category, n_rows, cat_lt,
-                                         group_by_category, t, out_sum, out_count,
+                                         group_by_category, hot_rows, out_sum, out_count,
                                          (uint32_t *)(ws + skew::kFlagBytes), (int32_t *)ws, part,
                                          part ? workspace_bytes - need : 0, part_device(dev), s);
   if (e != hipSuccess) return hip_fail(e, "join launch");
