@@ -215,3 +215,44 @@ def test_stream_probe_rejects(lib):
     assert lib.stream_probe(ctypes.c_void_p(0x10004), 16, A2, S) == skew.SKEW_EINVAL  # not 16-byte aligned
     assert lib.stream_probe(ok, 20, A2, S) == skew.SKEW_EINVAL            # not a 16-byte multiple
     assert lib.stream_probe(ok, 16, ctypes.c_void_p(0x20004), S) == skew.SKEW_EINVAL  # output not 8-byte aligned
+
+
+def _star(lib, fn="star_join_batch", **kw):
+    a = dict(pk=A, uk=A2, qs=A, lt=A2, nq=4, price=A, cat=A2, n_prod=100, seg=A, n_cust=50, s=A, c=A2, ws=WS,
+             wsb=1 << 30)
+    a.update(kw)
+    head = (a["pk"], a["uk"], a["qs"], a["lt"], a["nq"], a["price"], a["cat"], a["n_prod"], a["seg"], a["n_cust"])
+    if fn == "star_join_batch":
+        return lib.star_join_batch(*head, None, a["s"], a["c"], a["ws"], a["wsb"], S)
+    best, ms = skew.StarTuning(), ctypes.c_float(0)
+    return lib.star_join_autotune(*head, a["s"], a["c"], ctypes.byref(best), ctypes.byref(ms), a["ws"], a["wsb"], S)
+
+
+@pytest.mark.parametrize("fn", ["star_join_batch", "star_join_autotune"])
+@pytest.mark.parametrize("kw,code", [
+    (dict(nq=0), skew.SKEW_EINVAL),
+    (dict(nq=4097), skew.SKEW_EINVAL),  # more queries than the tile table holds
+    (dict(n_prod=0), skew.SKEW_EINVAL),
+    (dict(n_cust=0), skew.SKEW_EINVAL),
+    (dict(pk=NULL), skew.SKEW_EINVAL),
+    (dict(lt=NULL), skew.SKEW_EINVAL),
+    (dict(seg=NULL), skew.SKEW_EINVAL),
+    (dict(c=NULL), skew.SKEW_EINVAL),
+    (dict(pk=ctypes.c_void_p(0x10004)), skew.SKEW_EINVAL),  # keys not 16-byte aligned
+    (dict(qs=ctypes.c_void_p(0x10004)), skew.SKEW_EINVAL),  # int64 table not 8-byte aligned
+    (dict(ws=WS_MIS), skew.SKEW_EINVAL),
+    (dict(wsb=1024), skew.SKEW_ENOSPACE),
+])
+def test_star_rejects(lib, fn, kw, code):
+    assert _star(lib, fn, **kw) == code
+
+
+def test_star_workspace_holds_the_customer_bitmaps(lib):
+    # one bitmap of min(n_cust, 2^20) bits per query on top of the product words and segment copy
+    small = lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 1, 2_000_000)
+    big = lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 65, 2_000_000)
+    assert big - small >= 64 * (1 << 20) // 8
+    assert big - small < 64 * (1 << 20) // 8 + 4096
+    # below 2^20 customers the bitmap is as long as the dimension
+    d = lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 9, 100_000) - lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 1, 100_000)
+    assert 8 * 100_000 // 8 <= d < 8 * 100_000 // 8 + 2048

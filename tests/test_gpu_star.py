@@ -205,3 +205,33 @@ def test_star_rejects_unaligned_keys(batch):
                              ctypes.c_void_p(out[0].data_ptr()), ctypes.c_void_p(out[1].data_ptr()),
                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), None)
     assert rc == skew.SKEW_EINVAL
+
+
+@pytest.fixture(scope="module")
+def many():
+    """The largest batch, 4096 queries of 0-3000 rows, with thresholds below, inside and above the segment range:
+    the tile table fills 16 KB of LDS, and workgroups stage a new query's bitmap on almost every tile."""
+    k, n_prod, n_cust, nq = 7, 50_000, 70_000, 4096
+    rng = np.random.default_rng(7)
+    sizes = rng.integers(0, 3001, nq).astype(np.int64)
+    sizes[::97] = 0
+    say(f"star batch of {nq} queries, {int(sizes.sum())} rows")
+    h = W.host_star_inputs(k, n_prod, n_cust, sizes)
+    lt = rng.integers(-5, 106, nq).astype(np.int32)
+    start = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    want = [oracle.star_join(h["prod"][a:b], h["cust"][a:b], h["price"], h["category"], h["cust_attr"], lt[q])
+            for q, (a, b) in enumerate(zip(start[:-1], start[1:]))]
+    ident = skew.StarBatch(to_dev(h["prod"]), to_dev(h["cust"]), to_dev(start), to_dev(lt), to_dev(h["price"]),
+                           to_dev(h["category"]), to_dev(h["cust_attr"]))
+    Lp = skew.build_skew_layout(ident.prod_keys, n_prod, ident.price, ident.category)
+    Lc = skew.build_skew_layout(ident.cust_keys, n_cust, None, ident.segment)
+    sk = skew.StarBatch(Lp.fact_recoded, Lc.fact_recoded, ident.query_start, ident.query_cust_lt, Lp.price,
+                        Lp.category, Lc.category)
+    return dict(identity=ident, skew=sk, want=want)
+
+
+@pytest.mark.parametrize("tun", [None, (-1, 70_000, 1024, 0), (0, 0, 4096, 2), (-1, 33, 2048, 0)], ids=str)
+@pytest.mark.parametrize("layout", ["skew", "identity"])
+def test_star_max_queries(many, tun, layout):
+    say(f"star 4096 queries {layout} tuning={tun}")
+    check(skew.star_join_batch(many[layout], None if tun is None else skew.StarTuning(*tun)), many["want"])
