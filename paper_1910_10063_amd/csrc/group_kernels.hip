@@ -268,9 +268,54 @@ struct PairSeg {  // this workgroup's segment; stores a chunk of (group, value) 
   }
 };
 
+// Narrow cold rows: over at most 2^20 groups, a cold row whose value lies in
+// [0, 2^12) travels as one 4-byte record, group << 12 | value, in a stream
+// of its own (segments, slice counts, scatter and pass 3), at half the bytes
+// of a (group, value) pair.  The other cold rows take the pair stream.  Both
+// streams share one slice table: rows [0, np) of the slice counts are the
+// narrow slices (np = P, or 0 when the groups do not fit), rows [np, np + P)
+// the pair slices, so one plan places both.
+constexpr int kNarrowShift = kGroupNarrowShift;
+constexpr uint32_t kNarrowValueLimit = 1u << kNarrowShift;
+constexpr int64_t kNarrowMaxGroups = 1LL << (32 - kNarrowShift);
+
+struct NarrowSeg {  // this workgroup's narrow segment
+  rsrc_t recs;
+  __device__ __forceinline__ void operator()(const uint32_t (&col)[1], int32_t idx, bool ok) const {
+    buffer_store_record((int32_t)col[0], recs, ok ? idx : -1, 0, 0, 0);
+  }
+};
+
+struct ColdOut {
+  ColdSink pair, narrow;  // shared slice counts, one item counter each
+  WaveChunk<2> cp;
+  WaveChunk<1> cn;
+  PairSeg seg;
+  NarrowSeg segn;
+  uint32_t np;  // narrow slices; 0: every cold row is a pair
+};
+
+// Cold rows to their stream: one chunk append per stream (a stream with no
+// row in the slot costs one ballot) and one count in the shared table.
+template <int N>
+__device__ __forceinline__ void cold_append_two(ColdOut &co, const uint32_t (&g)[N], const int32_t (&v)[N],
+                                                const bool (&cold)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const bool nw = cold[i] && co.np != 0u && (uint32_t)v[i] < kNarrowValueLimit;
+    const bool pr = cold[i] && !nw;
+    if (co.np != 0u) {  // uniform
+      const uint32_t rec[1] = {(g[i] << kNarrowShift) | (uint32_t)v[i]};
+      chunk_append(co.narrow, co.cn, nw, rec, co.segn);
+    }
+    const uint32_t pair[2] = {g[i], (uint32_t)v[i]};
+    chunk_append(co.pair, co.cp, pr, pair, co.seg);
+    lds_add_u32(&co.pair.hist[cold[i] ? (g[i] >> co.pair.wshift) + (nw ? 0u : co.np) : co.pair.sink], 1u);
+  }
+}
+
 template <int V>
-__device__ __forceinline__ void group_split_batch(GroupCtx &c, const ColdSink &o, WaveChunk<2> &ch,
-                                                  const PairSeg &seg, uint32_t hot_sink, const i32x4 (&x)[V],
+__device__ __forceinline__ void group_split_batch(GroupCtx &c, ColdOut &co, uint32_t hot_sink, const i32x4 (&x)[V],
                                                   const i32x4 (&y)[V], const bool (&valid)[V]) {
   uint32_t g[4 * V];
   int32_t v[4 * V];
@@ -290,33 +335,28 @@ __device__ __forceinline__ void group_split_batch(GroupCtx &c, const ColdSink &o
     cold[i] = in && !h;
     group_pack_or_sink(c, h, g[i], v[i], hot_sink);
   }
-  uint32_t cols[4 * V][2];
-#pragma unroll
-  for (int i = 0; i < 4 * V; ++i) {
-    cols[i][0] = g[i];
-    cols[i][1] = (uint32_t)v[i];
-  }
-  cold_append_dense(o, ch, g, cold, cols, seg);
+  cold_append_two(co, g, v, cold);
 }
 
-__device__ __forceinline__ void group_split_one(GroupCtx &c, const ColdSink &o, WaveChunk<2> &ch, const PairSeg &seg,
-                                                uint32_t hot_sink, bool valid, int32_t gi, int32_t v) {
+__device__ __forceinline__ void group_split_one(GroupCtx &c, ColdOut &co, uint32_t hot_sink, bool valid, int32_t gi,
+                                                int32_t vi) {
   const uint32_t g[1] = {(uint32_t)gi};
+  const int32_t v[1] = {vi};
   const bool in = valid && g[0] < (uint32_t)c.m;
   c.bad |= valid && !in;
-  const bool h = in && g[0] < (uint32_t)c.t && (uint32_t)v < kPackValueLimit;
+  const bool h = in && g[0] < (uint32_t)c.t && (uint32_t)vi < kPackValueLimit;
   const bool cold[1] = {in && !h};
-  group_pack_or_sink(c, h, g[0], v, hot_sink);
-  const uint32_t cols[1][2] = {{(uint32_t)gi, (uint32_t)v}};
-  cold_append_dense(o, ch, g, cold, cols, seg);
+  group_pack_or_sink(c, h, g[0], vi, hot_sink);
+  cold_append_two(co, g, v, cold);
 }
 
 __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
     const int32_t *__restrict__ keys, const int32_t *__restrict__ vals, int64_t n, int32_t m, int32_t t, int32_t P,
-    int32_t wshift, uint64_t *__restrict__ acc_sum, uint64_t *__restrict__ acc_cnt, int32_t *flag,
-    int32_t *__restrict__ seg_keys, int32_t *__restrict__ seg_vals, int64_t seg_cap, uint32_t *__restrict__ seg_count,
-    uint32_t *__restrict__ hist) {
+    int32_t wshift, int32_t np, uint64_t *__restrict__ acc_sum, uint64_t *__restrict__ acc_cnt, int32_t *flag,
+    int32_t *__restrict__ seg_keys, int32_t *__restrict__ seg_vals, int32_t *__restrict__ seg_recs, int64_t seg_cap,
+    uint32_t *__restrict__ seg_count, uint32_t *__restrict__ seg_count_n, uint32_t *__restrict__ hist) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const int32_t Q = np + P;  // rows of the slice table: narrow slices, then pair slices
   GroupCtx c;
   c.m = m;
   c.t = t;
@@ -326,23 +366,27 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
   c.bad = false;
   group_pack_init(c, smem);
   uint32_t *lhist = reinterpret_cast<uint32_t *>(c.pack + kCopySlots + t + kWave);
-  uint32_t *lcount = lhist + P + kWave;
-  for (int p = threadIdx.x; p < P + kWave; p += blockDim.x) lhist[p] = 0;
-  if (threadIdx.x == 0) *lcount = 0;
+  uint32_t *lcount = lhist + Q + kWave;  // [0]: pair items, [1]: narrow items
+  for (int p = threadIdx.x; p < Q + kWave; p += blockDim.x) lhist[p] = 0;
+  if (threadIdx.x < 2) lcount[threadIdx.x] = 0;
   __syncthreads();
-  ColdSink o;
-  o.count = lcount;
-  o.hist = lhist;
-  o.t = 0;  // slices of all groups
-  o.wshift = wshift;
-  o.sink = (uint32_t)P + lane_id();
-  PairSeg seg;
-  seg.keys = record_buffer(seg_keys + (int64_t)blockIdx.x * seg_cap, (uint32_t)seg_cap);
-  seg.vals = record_buffer(seg_vals + (int64_t)blockIdx.x * seg_cap, (uint32_t)seg_cap);
+  ColdOut co;
+  co.pair.count = lcount;
+  co.pair.hist = lhist;
+  co.pair.t = 0;  // slices of all groups
+  co.pair.wshift = wshift;
+  co.pair.sink = (uint32_t)Q + lane_id();
+  co.narrow = co.pair;
+  co.narrow.count = lcount + 1;
+  co.np = (uint32_t)np;
+  co.seg.keys = record_buffer(seg_keys + (int64_t)blockIdx.x * seg_cap, (uint32_t)seg_cap);
+  co.seg.vals = record_buffer(seg_vals + (int64_t)blockIdx.x * seg_cap, (uint32_t)seg_cap);
+  co.segn.recs = record_buffer(seg_recs + (int64_t)blockIdx.x * seg_cap, np ? (uint32_t)seg_cap : 0u);
   const uint32_t hot_sink = (uint32_t)(kCopySlots + t) + lane_id();
-  WaveChunk<2> ch;
-  ch.n = 0;
-  ch.col[0] = ch.col[1] = 0;
+  co.cp.n = 0;
+  co.cp.col[0] = co.cp.col[1] = 0;
+  co.cn.n = 0;
+  co.cn.col[0] = 0;
 
   // Workgroup b owns rows [b * per, (b + 1) * per) (in 4-row vectors when the
   // two columns are aligned together, else in single rows).
@@ -354,7 +398,7 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
       if (blockIdx.x == 0 && threadIdx.x < sp.head) i = threadIdx.x;
       if (blockIdx.x == gridDim.x - 1 && threadIdx.x >= 64 && threadIdx.x - 64 < n - sp.tail)
         i = sp.tail + threadIdx.x - 64;
-      group_split_one(c, o, ch, seg, hot_sink, i >= 0, i >= 0 ? keys[i] : 0, i >= 0 ? vals[i] : 0);
+      group_split_one(c, co, hot_sink, i >= 0, i >= 0 ? keys[i] : 0, i >= 0 ? vals[i] : 0);
     }
     const int64_t per = (sp.nvec + gridDim.x - 1) / gridDim.x;
     const int64_t vb = (int64_t)blockIdx.x * per < sp.nvec ? (int64_t)blockIdx.x * per : sp.nvec;
@@ -379,12 +423,12 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
     while (base < full_end) {  // the next tile is loaded while the current one is processed
       int64_t nxt = base + tile_vecs;
       load_tile(xb, yb, nxt < full_end ? nxt : base);
-      group_split_batch<kSplitVecs>(c, o, ch, seg, hot_sink, xa, ya, all_valid);
+      group_split_batch<kSplitVecs>(c, co, hot_sink, xa, ya, all_valid);
       base = nxt;
       if (base >= full_end) break;
       nxt = base + tile_vecs;
       load_tile(xa, ya, nxt < full_end ? nxt : base);
-      group_split_batch<kSplitVecs>(c, o, ch, seg, hot_sink, xb, yb, all_valid);
+      group_split_batch<kSplitVecs>(c, co, hot_sink, xb, yb, all_valid);
       base = nxt;
     }
     if (full_end < ve) {  // last partial tile
@@ -397,7 +441,7 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
         x[u] = valid[u] ? load_stream4(vk + vi) : i32x4{0, 0, 0, 0};
         y[u] = valid[u] ? load_stream4(vv + vi) : i32x4{0, 0, 0, 0};
       }
-      group_split_batch<kSplitVecs>(c, o, ch, seg, hot_sink, x, y, valid);
+      group_split_batch<kSplitVecs>(c, co, hot_sink, x, y, valid);
     }
   } else {
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
@@ -406,25 +450,29 @@ __global__ __launch_bounds__(kGroupThreads) void group_split_kernel(
     for (int64_t base = rb; base < re; base += blockDim.x) {
       const int64_t i = base + threadIdx.x;
       const bool valid = i < re;
-      group_split_one(c, o, ch, seg, hot_sink, valid, valid ? load_stream1(keys + i) : 0,
+      group_split_one(c, co, hot_sink, valid, valid ? load_stream1(keys + i) : 0,
                       valid ? load_stream1(vals + i) : 0);
     }
   }
-  chunk_drain(o, ch, seg);
+  chunk_drain(co.pair, co.cp, co.seg);
+  if (np) chunk_drain(co.narrow, co.cn, co.segn);
   if (c.bad) *flag = 1;
   __syncthreads();
-  if (threadIdx.x == 0) seg_count[blockIdx.x] = *lcount < seg_cap ? *lcount : (uint32_t)seg_cap;
-  for (int p = threadIdx.x; p < P; p += blockDim.x) hist[(int64_t)p * gridDim.x + blockIdx.x] = lhist[p];
+  if (threadIdx.x == 0) seg_count[blockIdx.x] = lcount[0] < seg_cap ? lcount[0] : (uint32_t)seg_cap;
+  if (threadIdx.x == 1) seg_count_n[blockIdx.x] = lcount[1] < seg_cap ? lcount[1] : (uint32_t)seg_cap;
+  for (int p = threadIdx.x; p < Q; p += blockDim.x) hist[(int64_t)p * gridDim.x + blockIdx.x] = lhist[p];
   group_pack_flush(c);
 }
 
 // ---------------------------------------------------------------------------
-// Partitioned form, pass 3: the slice-ordered pairs (2-byte group offsets
-// inside their slice, 4-byte values) are cut into one contiguous share per
-// workgroup, balanced over pairs plus the cost of flushing each slice; the
-// workgroup sums the pairs of each slice its share touches in LDS bins (W
+// Partitioned form, pass 3, one launch per stream: the slice-ordered items
+// (pairs: 2-byte group offsets inside their slice and 4-byte values; narrow:
+// one word, offset << 12 | value) are cut into one contiguous share per
+// workgroup, balanced over items plus the cost of flushing each slice; the
+// workgroup sums the items of each slice its share touches in LDS bins (W
 // groups) and flushes the bins into the shared accumulators before it moves
-// to the next slice.
+// to the next slice.  slice_off[0..P] are positions in the item arrays (the
+// pair stream's start after the narrow items).
 // ---------------------------------------------------------------------------
 constexpr int kSliceVecs = 2;  // 8-pair vectors per lane per batch
 
@@ -446,6 +494,7 @@ __device__ __forceinline__ void slice_flush(uint64_t *bsum, uint32_t *bcnt, int3
   }
 }
 
+template <bool NARROW>
 __global__ __launch_bounds__(kGroupThreads) void group_slice_kernel(
     const uint16_t *__restrict__ locals, const int32_t *__restrict__ vals, const uint32_t *__restrict__ slice_off,
     int32_t P, int32_t m, int32_t t, int32_t wshift, uint64_t *__restrict__ acc_sum, uint64_t *__restrict__ acc_cnt) {
@@ -458,22 +507,40 @@ __global__ __launch_bounds__(kGroupThreads) void group_slice_kernel(
     bsum[i] = 0;
     bcnt[i] = 0;
   }
-  for (int p = threadIdx.x; p <= P; p += blockDim.x) soff[p] = slice_off[p];
+  const uint32_t first = slice_off[0];  // items of this stream are [first, slice_off[P])
+  for (int p = threadIdx.x; p <= P; p += blockDim.x) soff[p] = slice_off[p] - first;
   __syncthreads();
   uint32_t lo, hi;
   balanced_share(soff, P, 2u * (uint32_t)W, blockIdx.x, gridDim.x, &lo, &hi);
   int32_t p = lo < hi ? slice_of_item(soff, P, lo) : P;
+  lo += first;  // back to positions in the item arrays (16-byte aligned at position 0)
+  hi += first;
   const i32x4 *vl = reinterpret_cast<const i32x4 *>(locals);
   const i32x4 *vv = reinterpret_cast<const i32x4 *>(vals);
   auto add = [&](uint32_t local, int32_t v) {  // local < W by construction
     lds_add_u64(&bsum[local], (uint64_t)(int64_t)v);
     lds_add_u32(&bcnt[local], 1u);
   };
+  auto add_rec = [&](uint32_t r) { add(r >> kNarrowShift, (int32_t)(r & (kNarrowValueLimit - 1u))); };
   for (uint32_t at = lo; at < hi; ++p) {
-    const uint32_t end = soff[p + 1] < hi ? soff[p + 1] : hi;
+    const uint32_t end = soff[p + 1] + first < hi ? soff[p + 1] + first : hi;
     if (end <= at) continue;
     const int64_t sbase = (int64_t)t + ((int64_t)p << wshift);
     const int32_t slen = (int32_t)((int64_t)m - sbase < W ? (int64_t)m - sbase : W);
+    if (NARROW) {
+      walk_items<4, 2 * kSliceVecs, kGroupThreads, i32x4>(
+          at, end, [&](uint32_t i) { add_rec((uint32_t)vals[i]); }, [&](uint32_t vi) { return load_stream4(vv + vi); },
+          [&](const i32x4(&x)[2 * kSliceVecs], const bool(&valid)[2 * kSliceVecs]) {
+#pragma unroll
+            for (int u = 0; u < 2 * kSliceVecs; ++u) {
+              if (!valid[u]) continue;
+              add_rec((uint32_t)x[u].x);
+              add_rec((uint32_t)x[u].y);
+              add_rec((uint32_t)x[u].z);
+              add_rec((uint32_t)x[u].w);
+            }
+          });
+    } else {
     walk_items<8, kSliceVecs, kGroupThreads, PairVec>(
         at, end, [&](uint32_t i) { add(locals[i], vals[i]); },
         [&](uint32_t vi) { return PairVec{load_stream4(vl + vi), load_stream4(vv + 2 * vi), load_stream4(vv + 2 * vi + 1)}; },
@@ -491,6 +558,7 @@ __global__ __launch_bounds__(kGroupThreads) void group_slice_kernel(
             }
           }
         });
+    }
     __syncthreads();
     slice_flush(bsum, bcnt, slen, sbase, acc_sum, acc_cnt);
     __syncthreads();
@@ -563,13 +631,20 @@ GroupPlan group_plan(int64_t n_fact, int32_t n_groups, const DeviceInfo &dev) {
   return pl;
 }
 
+int32_t group_narrow_slices(const GroupPlan &pl) {
+  return ((int64_t)pl.slices << pl.wshift) <= kNarrowMaxGroups ? pl.slices : 0;
+}
+
 size_t group_partition_bytes(const GroupPlan &pl) {
   auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const int32_t P = pl.slices > 0 ? pl.slices : 1;
-  return 2 * r((size_t)pl.blocks * pl.seg_cap * 4)  // cold segments (keys, values)
-         + r((size_t)pl.round * 2 + 16)             // slice-ordered group offsets (2 bytes)
-         + r((size_t)pl.round * 4 + 16)             // slice-ordered values
-         + r((size_t)P * pl.blocks * 4) + r((size_t)P * 4) + r(4) + r((size_t)pl.blocks * 4) + r((size_t)(P + 1) * 4);
+  const int32_t Q = (pl.slices > 0 ? pl.slices : 1) + group_narrow_slices(pl);
+  const size_t seg = r((size_t)pl.blocks * pl.seg_cap * 4);
+  return 2 * seg                                     // pair segments (keys, values)
+         + (group_narrow_slices(pl) ? seg : 0)       // narrow segments
+         + r((size_t)pl.round * 2 + 16)              // slice-ordered group offsets of pairs (2 bytes)
+         + r((size_t)pl.round * 4 + 16)              // slice-ordered values of pairs, and narrow items
+         + r((size_t)Q * pl.blocks * 4) + r((size_t)Q * 4) + r(4) + 2 * r((size_t)pl.blocks * 4) +
+         r((size_t)(Q + 1) * 4);
 }
 
 hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact, int32_t n_groups, GroupMode mode,
@@ -588,12 +663,14 @@ hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact
   if (e != hipSuccess) return e;
   if (n_fact > 0) {
     const GroupPlan pl = group_plan(n_fact, n_groups, dev);
+    const int32_t np = group_narrow_slices(pl);
+    const int32_t Q = np + pl.slices;  // rows of the shared slice table
     const bool partitioned = mode != kGroupAtomic && part_ws && n_fact >= kPartitionMinFact && pl.slices > 0 &&
-                             pl.slices <= kMaxSlices && part_bytes >= group_partition_bytes(pl);
+                             Q <= kMaxSlices && part_bytes >= group_partition_bytes(pl);
     // t is clamped to the LDS capacity of the form that runs
     int32_t t = hot_groups;
     if (mode == kGroupRange) {
-      const int32_t cap = partitioned ? group_split_max_hot_groups(pl.slices, dev) : group_max_hot_groups(dev);
+      const int32_t cap = partitioned ? group_split_max_hot_groups(Q, dev) : group_max_hot_groups(dev);
       if (t > cap) t = cap;
       if (t > n_groups) t = n_groups;
       if (t < 0) t = 0;
@@ -632,44 +709,59 @@ hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact
       ws += r((size_t)pl.blocks * pl.seg_cap * 4);
       int32_t *seg_v = (int32_t *)ws;
       ws += r((size_t)pl.blocks * pl.seg_cap * 4);
+      int32_t *seg_n = (int32_t *)ws;
+      if (np) ws += r((size_t)pl.blocks * pl.seg_cap * 4);
       uint16_t *items_k = (uint16_t *)ws;
       ws += r((size_t)pl.round * 2 + 16);
       int32_t *items_v = (int32_t *)ws;
       ws += r((size_t)pl.round * 4 + 16);
-      SliceTables tab;
+      SliceTables tab;  // both streams: narrow slices [0, np), pair slices [np, Q)
       tab.hist = (uint32_t *)ws;
-      ws += r((size_t)pl.slices * pl.blocks * 4);
+      ws += r((size_t)Q * pl.blocks * 4);
       tab.row_total = (uint32_t *)ws;
-      ws += r((size_t)pl.slices * 4);
+      ws += r((size_t)Q * 4);
       tab.total = (uint32_t *)ws;
       ws += r(4);
-      tab.seg_count = (uint32_t *)ws;
+      tab.seg_count = (uint32_t *)ws;  // pair items per block
+      ws += r((size_t)pl.blocks * 4);
+      uint32_t *seg_count_n = (uint32_t *)ws;  // narrow items per block
       ws += r((size_t)pl.blocks * 4);
       tab.slice_off = (uint32_t *)ws;
-      const size_t lds1 = group_split_lds_bytes(t, pl.slices);
-      const size_t lds3 = ((size_t)12 << pl.wshift) + (size_t)(pl.slices + 1) * 4;
+      SliceTables tab_n = tab;  // the narrow stream's view
+      tab_n.seg_count = seg_count_n;
+      SliceTables tab_p = tab;  // the pair stream's view
+      tab_p.hist = tab.hist + (size_t)np * pl.blocks;
+      tab_p.slice_off = tab.slice_off + np;
+      const size_t lds1 = group_split_lds_bytes(t, Q);
+      const size_t lds3 = ((size_t)12 << pl.wshift) + (size_t)(Q + 1) * 4;
       allow_lds(group_split_kernel, lds1);
-      allow_lds(group_slice_kernel, lds3);
+      allow_lds(group_slice_kernel<false>, lds3);
+      allow_lds(group_slice_kernel<true>, lds3);
       for (int64_t off = 0; off < n_fact; off += pl.round) {
         const int64_t n = n_fact - off < pl.round ? n_fact - off : pl.round;
         st = stage_begin("group_split", s);
         hipLaunchKernelGGL(group_split_kernel, dim3(pl.blocks), dim3(kGroupThreads), lds1, s, keys + off, vals + off,
-                           n, n_groups, t, pl.slices, pl.wshift, acc_sum, acc_cnt, flag, seg_k, seg_v, pl.seg_cap,
-                           tab.seg_count, tab.hist);
+                           n, n_groups, t, pl.slices, pl.wshift, np, acc_sum, acc_cnt, flag, seg_k, seg_v, seg_n,
+                           pl.seg_cap, tab.seg_count, seg_count_n, tab.hist);
         e = hipGetLastError();
         stage_end(st, s);
         st = stage_begin("group_plan", s);
-        if (e == hipSuccess) e = launch_partition_plan(tab, pl.slices, pl.blocks, s);
+        if (e == hipSuccess) e = launch_partition_plan(tab, Q, pl.blocks, s);
         stage_end(st, s);
         st = stage_begin("group_scatter", s);
+        if (e == hipSuccess && np)
+          e = launch_partition_scatter_narrow(tab_n, np, pl.blocks, seg_n, pl.seg_cap, pl.wshift, items_v, s);
         if (e == hipSuccess)
-          e = launch_partition_scatter(tab, pl.slices, pl.blocks, seg_k, seg_v, pl.seg_cap, 0, pl.wshift, items_k,
+          e = launch_partition_scatter(tab_p, pl.slices, pl.blocks, seg_k, seg_v, pl.seg_cap, 0, pl.wshift, items_k,
                                        items_v, s);
         stage_end(st, s);
         if (e != hipSuccess) return e;
         st = stage_begin("group_slice", s);
-        hipLaunchKernelGGL(group_slice_kernel, dim3(pl.blocks), dim3(kGroupThreads), lds3, s, items_k, items_v,
-                           tab.slice_off, pl.slices, n_groups, 0, pl.wshift, acc_sum, acc_cnt);
+        if (np)
+          hipLaunchKernelGGL(group_slice_kernel<true>, dim3(pl.blocks), dim3(kGroupThreads), lds3, s, items_k, items_v,
+                             tab_n.slice_off, np, n_groups, 0, pl.wshift, acc_sum, acc_cnt);
+        hipLaunchKernelGGL(group_slice_kernel<false>, dim3(pl.blocks), dim3(kGroupThreads), lds3, s, items_k, items_v,
+                           tab_p.slice_off, pl.slices, n_groups, 0, pl.wshift, acc_sum, acc_cnt);
         e = hipGetLastError();
         stage_end(st, s);
         if (e != hipSuccess) return e;

@@ -44,6 +44,12 @@ hipError_t launch_partition_plan(const SliceTables &tab, int32_t P, int32_t B, h
 hipError_t launch_partition_scatter(const SliceTables &tab, int32_t P, int32_t B, const int32_t *seg_keys,
                                     const int32_t *seg_vals, int64_t seg_cap, int32_t t, int32_t wshift,
                                     uint16_t *out_local, int32_t *out_vals, hipStream_t s);
+// The group-by's narrow records: group << kGroupNarrowShift | value in the
+// segments, (group offset inside its slice) << kGroupNarrowShift | value in
+// slice order (out_items), slices of 1 << wshift groups from group 0.
+constexpr int kGroupNarrowShift = 12;
+hipError_t launch_partition_scatter_narrow(const SliceTables &tab, int32_t P, int32_t B, const int32_t *seg_recs,
+                                           int64_t seg_cap, int32_t wshift, int32_t *out_items, hipStream_t s);
 
 // Partitioned key histogram (large fact columns, at most kMaxSlices slices of
 // 32768 keys).  counts must be zeroed; keys outside [0, n_keys) set *flag.

@@ -146,8 +146,9 @@ __global__ __launch_bounds__(kMaxSlices) void slice_plan_kernel(const uint32_t *
 // ---------------------------------------------------------------------------
 // Scatter: block b moves the cold items of its segment to their slice-order
 // positions, as 2-byte offsets inside their slice ((k - t) & (W - 1)) plus the
-// value when there is one.  Items are first sorted by slice inside LDS, one
-// tile at a time, so that consecutive lanes write consecutive slots.
+// value when there is one; a narrow record (group << 12 | value, t = 0) moves
+// as one word, offset << 12 | value.  Items are first sorted by slice inside
+// LDS, one tile at a time, so that consecutive lanes write consecutive slots.
 // ---------------------------------------------------------------------------
 constexpr int kScatterThreads = 1024;
 constexpr int kScatterVecs = 4;                          // 16-byte loads per thread per tile
@@ -156,7 +157,7 @@ constexpr int kScatterTile = kScatterThreads * kScatterPer;
 
 size_t scatter_lds_bytes(bool pairs) { return (size_t)kScatterTile * 4 * (pairs ? 2 : 1); }
 
-template <bool PAIRS>
+template <bool PAIRS, bool NARROW = false>
 __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
     const int32_t *__restrict__ seg_keys, const int32_t *__restrict__ seg_vals, int64_t seg_cap,
     const uint32_t *__restrict__ seg_count, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ slice_off,
@@ -175,8 +176,9 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
   const i32x4 *sk = reinterpret_cast<const i32x4 *>(seg_keys + (int64_t)b * seg_cap);
   const i32x4 *sv = reinterpret_cast<const i32x4 *>(PAIRS ? seg_vals + (int64_t)b * seg_cap : seg_keys);
   const uint32_t wmask = (1u << wshift) - 1u;
+  auto key_of = [&](int32_t k) -> int32_t { return NARROW ? (int32_t)((uint32_t)k >> kGroupNarrowShift) : k; };
   auto slice_of = [&](int32_t k) -> uint32_t {
-    const uint32_t p = (uint32_t)(k - t) >> wshift;
+    const uint32_t p = (uint32_t)(key_of(k) - t) >> wshift;
     return p < (uint32_t)P ? p : (uint32_t)P - 1;  // pass 1 only writes ids in [t, t + P * W)
   };
   // The next tile is loaded into registers while the current tile is sorted
@@ -250,8 +252,13 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
       const int32_t kk = skey[j];
       const uint32_t p = slice_of(kk);
       const uint32_t g = run[p] + (j - start[p]);
-      out_local[g] = (uint16_t)((uint32_t)(kk - t) & wmask);
-      if (PAIRS) out_vals[g] = sval[j];
+      if (NARROW) {
+        const uint32_t vmask = (1u << kGroupNarrowShift) - 1u;
+        out_vals[g] = (int32_t)((((uint32_t)key_of(kk) & wmask) << kGroupNarrowShift) | ((uint32_t)kk & vmask));
+      } else {
+        out_local[g] = (uint16_t)((uint32_t)(kk - t) & wmask);
+        if (PAIRS) out_vals[g] = sval[j];
+      }
     }
     __syncthreads();
     if (tid < P) run[tid] += c;
@@ -651,6 +658,16 @@ hipError_t launch_partition_scatter(const SliceTables &tab, int32_t P, int32_t B
     hipLaunchKernelGGL(scatter_kernel<false>, dim3(B), dim3(kScatterThreads), lds, s, seg_keys, seg_vals, seg_cap,
                        tab.seg_count, tab.hist, tab.slice_off, P, t, wshift, out_local, out_vals);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_partition_scatter_narrow(const SliceTables &tab, int32_t P, int32_t B, const int32_t *seg_recs,
+                                           int64_t seg_cap, int32_t wshift, int32_t *out_items, hipStream_t s) {
+  const size_t lds = scatter_lds_bytes(false);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(scatter_kernel<false, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((scatter_kernel<false, true>), dim3(B), dim3(kScatterThreads), lds, s, seg_recs, nullptr, seg_cap,
+                     tab.seg_count, tab.hist, tab.slice_off, P, 0, wshift, nullptr, out_items);
   return hipGetLastError();
 }
 

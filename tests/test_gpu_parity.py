@@ -358,6 +358,36 @@ def test_partitioned_group_value_boundaries(offset):
     assert skew.query_status(ws) == skew.SKEW_OK
 
 
+@pytest.mark.parametrize("M", [40_000, 1 << 20, (1 << 20) + 1])
+@pytest.mark.parametrize("mix", ["edges", "narrow_only", "wide_only"])
+def test_partitioned_group_narrow_records(M, mix):
+    """Cold rows of the partitioned group-by travel as one word (group << 12 | value) when there are at most 2^20
+    groups and the value lies in [0, 2^12), else as a (group, value) pair; values at and around both limits, with
+    either stream empty, and group counts on both sides of 2^20."""
+    say(f"group narrow records M={M} mix={mix}")
+    rng = np.random.default_rng(M % 1000 + len(mix))
+    F = (1 << 22) + 77
+    keys = (rng.zipf(1.05, F) % M).astype(np.int32)
+    keys[rng.random(F) < 0.01] = M - 1  # the last group, in the last slice
+    if mix == "edges":
+        edge = np.array([0, 1, 4094, 4095, 4096, 4097, 65535, 65536, -1, 2**31 - 1, -2**31], np.int64)
+        vals = edge[rng.integers(0, edge.size, F)].astype(np.int32)
+        narrow = rng.random(F) < 0.5
+        vals[narrow] = rng.integers(0, 4096, int(narrow.sum()))
+    elif mix == "narrow_only":
+        vals = rng.integers(0, 4096, F).astype(np.int32)
+    else:
+        vals = rng.integers(4096, 1 << 20, F).astype(np.int32)
+    es, ec, inv = oracle.group_aggregate(keys, vals, M)
+    assert inv == 0
+    kd, vd = to_dev(keys), to_dev(vals)
+    ws = skew.workspace(skew.SKEW_OP_GROUP, F, M, DEV)
+    for t in (0, 16, skew.SKEW_HOT_AUTO):
+        s, c = skew.group_aggregate(kd, vd, M, hot_groups=t, ws=ws)
+        assert (host(s) == es).all() and (host(c) == ec).all(), t
+    assert skew.query_status(ws) == skew.SKEW_OK
+
+
 def test_generator_device_matches_host():
     say("generator: device vs host")
     for n_ranks, s in ((100_000, 1.0), (1_000_000, 1.1), (1000, 0.0)):
