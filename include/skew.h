@@ -151,7 +151,11 @@ int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *d
  *                       LDS (workspace of SKEW_OP_GROUP size) or sent to global
  *                       atomics (single-pass workspace).  In the partitioned
  *                       form a bin takes rows with values in [0, 2^16); a hot
- *                       row with another value is partitioned like a cold one.  0: no id-based
+ *                       row with another value is partitioned like a cold one.
+ *                       Partitioned rows with values in [0, 2^12) over at most
+ *                       2^20 groups move as 4-byte records, the others as
+ *                       (group, value) pairs; the results do not depend on
+ *                       which.  0: no id-based
  *                       privatisation, the layout-oblivious method: every row
  *                       partitioned (large workspace) or an LDS hash table of
  *                       the first groups met (single pass).  SKEW_HOT_NONE:
