@@ -208,9 +208,10 @@ __global__ __launch_bounds__(kGroupThreads) void group_kernel(const int32_t *__r
 
 // ---------------------------------------------------------------------------
 // Partitioned form, pass 1: rows of hot groups into LDS bins; every other
-// valid (group, value) pair appended to this workgroup's segment of the cold
-// buffer and counted in its slice (g >> wshift; slices cover all groups, so
-// that a hot row the bins cannot take is resolved like a cold one).
+// valid row appended to this workgroup's segment of the cold buffer of its
+// stream (4-byte records or pairs, below) and counted in its slice
+// (g >> wshift; slices cover all groups, so that a hot row the bins cannot
+// take is resolved like a cold one).
 //
 // A bin is one 64-bit word, count << 40 | sum, updated by a single LDS atomic.
 // It takes rows whose value lies in [0, 2^16); it stays exact while it sees
