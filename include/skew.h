@@ -13,6 +13,9 @@
  *   256-byte aligned).
  * - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on it
  *   in order; unless stated otherwise a call returns without waiting.
+ *   fk_join_aggregate, group_aggregate and star_join_batch enqueue kernels
+ *   only (no memset or copy), so a caller may capture them in a HIP graph
+ *   (with SKEW_CHECK unset, which adds a wait for the error flag).
  * - Keys and groups are 0-based offsets (Section 2.2: a foreign key is an
  *   array offset into the dimension table).
  * - All sums and counts are exact 64-bit integers (no floating point).
