@@ -68,13 +68,23 @@ __global__ __launch_bounds__(kBitsThreads) void star_bits_kernel(const uint4 *__
   }
 }
 
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
 // Tile table: tiles of query q start at tile_start[q]; outputs and the queue
 // counter are cleared (one workgroup, n_queries <= kMaxStarQueries).
 __global__ __launch_bounds__(1024) void star_plan_kernel(const int64_t *__restrict__ qstart, int32_t nq,
                                                          int64_t tile_rows, uint32_t *__restrict__ tile_start,
                                                          uint32_t *__restrict__ counter, int64_t *__restrict__ out_sum,
                                                          int64_t *__restrict__ out_cnt, int32_t *flag) {
-  __shared__ uint32_t part[1024];
+  __shared__ uint32_t part[64];  // [0, 16): wave totals, [32, 48): their exclusive prefixes
   for (int i = threadIdx.x; i < nq * 16; i += blockDim.x) {
     out_sum[i] = 0;
     out_cnt[i] = 0;
@@ -83,7 +93,7 @@ __global__ __launch_bounds__(1024) void star_plan_kernel(const int64_t *__restri
     *counter = 0;
     *flag = 0;
   }
-  // exclusive scan of the tile counts, kStarQueriesPerThread queries per thread
+  // tile counts of this thread's queries (ceil(nq / 1024) consecutive ones)
   const int per = (nq + 1023) / 1024;
   const int q0 = threadIdx.x * per;
   uint32_t sum = 0;
@@ -91,19 +101,18 @@ __global__ __launch_bounds__(1024) void star_plan_kernel(const int64_t *__restri
     const int64_t n = qstart[q + 1] - qstart[q];
     sum += n > 0 ? (uint32_t)((n + tile_rows - 1) / tile_rows) : 0u;
   }
-  part[threadIdx.x] = sum;
+  // exclusive scan over the 1024 threads: within each wave, then over the 16 wave totals
+  const uint32_t incl = wave_inclusive_scan(sum);
+  if (lane_id() == kWave - 1) part[threadIdx.x / kWave] = incl;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int i = 0; i < 1024; ++i) {
-      const uint32_t v = part[i];
-      part[i] = run;
-      run += v;
-    }
-    tile_start[nq] = run;
+  if (threadIdx.x < kWave) {
+    const uint32_t w = threadIdx.x < 1024 / kWave ? part[threadIdx.x] : 0u;
+    const uint32_t wi = wave_inclusive_scan(w);
+    if (threadIdx.x < 1024 / kWave) part[32 + threadIdx.x] = wi - w;
+    if (threadIdx.x == 1024 / kWave - 1) tile_start[nq] = wi;
   }
   __syncthreads();
-  uint32_t run = part[threadIdx.x];
+  uint32_t run = part[32 + threadIdx.x / kWave] + incl - sum;
   for (int q = q0; q < q0 + per && q < nq; ++q) {
     tile_start[q] = run;
     const int64_t n = qstart[q + 1] - qstart[q];
