@@ -20,15 +20,27 @@ __global__ void join_pack_kernel(const int32_t *__restrict__ price, const int8_t
     out_cnt[gid] = 0;
   }
   if (gid == 0) *flag = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t r = gid; r < n_rows; r += stride) {
-    const int32_t p = price[r];
+  auto pack = [&](int32_t p, int32_t c) -> uint32_t {
     int32_t g;
-    uint32_t w = kValid;
-    if (row_group(cat[r], cat_lt, by_cat, &g))
-      w = ((uint32_t)p <= kPriceMask) ? (kValid | ((uint32_t)(g + 1) << kGroupShift) | (uint32_t)p) : 0u;
-    words[r] = w;
+    if (!row_group(c, cat_lt, by_cat, &g)) return kValid;
+    return ((uint32_t)p <= kPriceMask) ? (kValid | ((uint32_t)(g + 1) << kGroupShift) | (uint32_t)p) : 0u;
+  };
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t done = 0;  // rows [0, done) packed four at a time
+  if ((((uintptr_t)price & 15u) | ((uintptr_t)cat & 3u) | ((uintptr_t)words & 15u)) == 0) {
+    const int64_t nv = n_rows / 4;
+    const i32x4 *p4 = reinterpret_cast<const i32x4 *>(price);
+    const uint32_t *c4 = reinterpret_cast<const uint32_t *>(cat);
+    uint4 *w4 = reinterpret_cast<uint4 *>(words);
+    for (int64_t v = gid; v < nv; v += stride) {
+      const i32x4 p = load_stream4(p4 + v);
+      const uint32_t c = c4[v];
+      w4[v] = uint4{pack(p.x, (int8_t)c), pack(p.y, (int8_t)(c >> 8)), pack(p.z, (int8_t)(c >> 16)),
+                    pack(p.w, (int8_t)(c >> 24))};
+    }
+    done = 4 * nv;
   }
+  for (int64_t r = done + gid; r < n_rows; r += stride) words[r] = pack(price[r], cat[r]);
 }
 
 constexpr int kJoinVecs = 4;  // 16-byte key vectors per lane per batch
@@ -559,7 +571,7 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
                        hipStream_t s) {
   const int groups = by_cat ? 16 : 1;
   StageTimer st = stage_begin("join_pack", s);
-  hipLaunchKernelGGL(join_pack_kernel, dim3(grid_1d(n_rows > 16 ? n_rows : 16, 256, dev.cu_count * 16)), dim3(256), 0,
+  hipLaunchKernelGGL(join_pack_kernel, dim3(grid_1d(n_rows / 4 > 16 ? n_rows / 4 : 16, 256, dev.cu_count * 16)), dim3(256), 0,
                      s, price, cat, n_rows, cat_lt, by_cat, words, out_sum, out_cnt, flag);
   hipError_t e = hipGetLastError();
   stage_end(st, s);
