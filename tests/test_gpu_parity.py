@@ -423,3 +423,24 @@ def test_partitioned_join_with_gathered_tail():
             s, c = skew.fk_join_aggregate(fd, pd, cd, cat_lt, by_cat, hot_rows=t, ws=ws)
             assert (host(s) == es).all() and (host(c) == ec).all(), (by_cat, t)
     assert skew.query_status(ws) == skew.SKEW_OK
+
+
+@pytest.mark.parametrize("F", [70_001, (1 << 22) + 3])
+@pytest.mark.parametrize("poff,coff", [(0, 0), (1, 0), (0, 3), (3, 1)])
+def test_join_dimension_columns_at_any_alignment(F, poff, coff):
+    """The dimension is packed four rows at a time when the price column is 16-byte aligned and the categories
+    4-byte aligned, one row at a time otherwise; a ragged dimension (N % 4 = 1) and both forms of the query."""
+    say(f"join dimension alignment F={F} poff={poff} coff={coff}")
+    N = 50_001
+    h = W.host_join_inputs(12, N, F, 1.0)
+    price = torch.zeros(N + 4, dtype=torch.int32, device=DEV)
+    cat = torch.zeros(N + 4, dtype=torch.int8, device=DEV)
+    price[poff:poff + N] = to_dev(h["price"])
+    cat[coff:coff + N] = to_dev(h["category"])
+    pv, cv = price[poff:poff + N], cat[coff:coff + N]
+    keys = to_dev(h["fact"])
+    for cat_lt, by_cat in ((16, True), (4, False)):
+        es, ec = oracle.fk_join_aggregate(h["fact"], h["price"], h["category"], cat_lt, by_cat)
+        for t in (0, 1000, skew.SKEW_HOT_AUTO):
+            s, c = skew.fk_join_aggregate(keys, pv, cv, cat_lt, by_cat, hot_rows=t)
+            assert (host(s) == es).all() and (host(c) == ec).all(), (cat_lt, t)
