@@ -161,3 +161,18 @@ def test_recode_hot_keys_colliding_buckets():
     ref = oracle.build_layout(fact, N)
     L = skew.build_skew_layout(to_dev(fact), N)
     check(L, ref)
+
+
+@pytest.mark.parametrize("in_place", [False, True])
+def test_recode_crowded_low_keys(in_place):
+    """A column of more than 2^24 keys with most keys in the first eighth of the domain, a ragged end (length
+    3 mod 4), in place and into a separate column."""
+    N, F = 3_000_000, (1 << 24) + (1 << 22) + 3
+    say(f"recode, crowded low keys, in_place={in_place}")
+    rng = np.random.default_rng(21)
+    fact = rng.integers(0, N, F).astype(np.int32)
+    low = rng.random(F) < 0.8
+    fact[low] = rng.integers(0, N // 8, int(low.sum())).astype(np.int32)
+    ref = oracle.build_layout(fact, N)
+    L = skew.build_skew_layout(to_dev(fact), N, in_place=in_place)
+    check(L, ref)
