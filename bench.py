@@ -54,10 +54,10 @@ PAPER_CONTEXT = {
     "gpu_numbers": None,
 }
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "join_split_traffic.json")
-# sources of the dominant kernel (the join's pass 1): its counters stay valid while these are unchanged
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "join_query_traffic.json")
+# sources of the query's kernels: the HBM byte counters stay valid while these are unchanged
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1910_10063_amd", "csrc", f)
-                  for f in ("join_kernels.hip", "query_common.h", "device_common.h")]
+                  for f in ("join_kernels.hip", "partition_kernels.hip", "query_common.h", "device_common.h")]
 
 
 def log(msg):
@@ -71,21 +71,29 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def timed(fn, steps, warmup, stream):
-    """Run fn warmup times, then time `steps` runs with HIP events on `stream`."""
+def timed_runs(fn, steps, warmup, stream):
+    """Run fn warmup times, then `steps` times back to back, each run between its own pair of HIP events
+    on `stream` (run i spans events i and i + 1, so no synchronisation separates the runs).  Returns the
+    per-run times in ms."""
     import torch
 
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
         fn()
-    b.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
-    return a.elapsed_time(b) / steps  # ms per run
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+
+
+def timed(fn, steps, warmup, stream):
+    """Median ms per run of `steps` individually event-timed runs after `warmup` untimed ones."""
+    import numpy as np
+
+    return float(np.median(timed_runs(fn, steps, warmup, stream)))
 
 
 def main():
@@ -219,41 +227,35 @@ def main():
 
     stages_skew = per_query(st_skew, KP)
     stages_ident = per_query(st_ident, KP)
-    # dominant kernel of the skew query and its algorithmic bytes per launch (what the stage must move at
-    # least): pass 1 streams 4 B per fact key, stages 4 B per hot dimension word and writes 4 B per cold
-    # key; the scatter reads 4 B and writes 2 B per cold key; pass 3 reads 2 B per cold key and the cold
-    # dimension words once (4 B each); the single pass streams 4 B per key plus the hot words; the pack
-    # reads 5 B and writes 4 B per dimension row.
+    # Roofline of the whole query (the hot-path table's algorithmic bytes: every fact key once, 4 B, and both
+    # dimension columns once, 5 B per row, plus the 16 x 2 int64 outputs) over the median query time, and,
+    # beside it, the dominant kernel on its own share: the keys one launch streams, 4 B each.
     dom = max(stages_skew, key=lambda k: stages_skew[k]["ms"])
     launches = stages_skew[dom]["launches"]
     hot_used = min(skew.max_hot_rows(True), N) if t_hot < 0 else min(t_hot, N)
     cold = int(cbr[hot_used:].to(torch.int64).sum().item())  # fact keys at or above the threshold
-    per_launch = {
-        "join_split": 4.0 * F / launches + 4.0 * hot_used + 4.0 * cold / launches,
-        "join_single_pass": 4.0 * F / launches + 4.0 * hot_used,
-        "join_scatter": 6.0 * cold / launches,
-        "join_slice": 2.0 * cold / launches + 4.0 * (N - hot_used),
-        "join_pack": 9.0 * N,
-        "join_plan": 0.0,
-    }
-    dom_bytes = per_launch.get(dom, 4.0 * F / launches)
+    keys_per_launch = F / launches
+    dom_bytes = {"join_split": 4.0 * keys_per_launch, "join_single_pass": 4.0 * keys_per_launch,
+                 "join_pack": 5.0 * N}.get(dom, 4.0 * keys_per_launch)
     dom_ms = stages_skew[dom]["ms"] / launches
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = None
+    dom_gbs = dom_bytes / (dom_ms * 1e-3) / 1e9
+    q_bytes = 4.0 * F + 5.0 * N + 256.0
+    q_gbs = q_bytes / (ms_skew * 1e-3) / 1e9
+    traffic, kernel_traffic = None, None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("source_sha") == kernel_source_sha() and tr.get("kernel") == dom and tr.get("n_fact") == F \
-                and tr.get("n_rows") == N and tr.get("zipf_s") == S:
-            traffic = tr.get("hbm_bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": dom_bytes, "kernel_ms": round(dom_ms, 4),
-                "launches_per_query": launches, "cold_fact_keys": cold,
-                "frac_of_read_probe": round(achieved / probe_gbs, 4)}
-    q_bytes = 4.0 * F + 9.0 * N  # whole query: every fact key once, both dimension columns once
-    query_roofline = {"bound": "hbm", "algorithmic_bytes": q_bytes,
-                      "achieved": round(q_bytes / (ms_skew * 1e-3) / 1e9, 1),
-                      "frac": round(q_bytes / (ms_skew * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if tr.get("source_sha") == kernel_source_sha() and tr.get("n_fact") == F and tr.get("n_rows") == N \
+                and tr.get("zipf_s") == S:
+            traffic = tr.get("hbm_bytes_per_query")
+            kernel_traffic = tr.get("kernels", {}).get(dom, {}).get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "scope": "whole query", "achieved": round(q_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(q_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes": q_bytes, "query_ms": round(ms_skew, 4),
+                "frac_of_read_probe": round(q_gbs / probe_gbs, 4),
+                "kernel": dom, "kernel_achieved": round(dom_gbs, 1), "kernel_frac": round(dom_gbs / HBM_PEAK_GBS, 4),
+                "kernel_algorithmic_bytes_per_launch": dom_bytes, "kernel_ms": round(dom_ms, 4),
+                "kernel_traffic": kernel_traffic, "launches_per_query": launches, "cold_fact_keys": cold,
+                "kernel_frac_of_read_probe": round(dom_gbs / probe_gbs, 4)}
 
     result = {
         "metric": METRIC,
@@ -263,6 +265,7 @@ def main():
         "steps": K,
         "warmup": WU,
         "ms_per_step": ms_skew,
+        "timing": "median of the individually event-timed steps",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -275,7 +278,6 @@ def main():
                    "seeds": {"fact": W.fact_seed(k), "perm": W.perm_seed(k), "price": W.price_seed(k),
                              "category": W.category_seed(k)}},
         "roofline": roofline,
-        "query_roofline": query_roofline,
         "paper_context": PAPER_CONTEXT,
         "read_probe": {"kernel": "stream_probe", "bytes": 4.0 * F, "ms": round(ms_probe, 4),
                        "GB_per_s": round(probe_gbs, 1), "frac_of_peak": round(probe_gbs / HBM_PEAK_GBS, 4)},
@@ -289,8 +291,8 @@ def main():
 
     if not args.no_extras:
         single_ws = skew.workspace(skew.SKEW_OP_JOIN_SINGLE_PASS, F, N, dev)
-        ms_sp = timed(query(Cp, pp, cp, t_hot, single_ws), max(K // 2, 3), 1, stream)
-        ms_sp_i = timed(query(C, price, cat, 0, single_ws), max(K // 2, 3), 1, stream)
+        ms_sp = timed(query(Cp, pp, cp, t_hot, single_ws), max(K // 2, 10), 1, stream)
+        ms_sp_i = timed(query(C, price, cat, 0, single_ws), max(K // 2, 10), 1, stream)
         result["single_pass"] = {"skew_tuples_per_s": F / (ms_sp * 1e-3), "identity_tuples_per_s": F / (ms_sp_i * 1e-3)}
         del single_ws
     if not args.no_extras:
@@ -298,13 +300,13 @@ def main():
         cap = skew.max_hot_rows(True)
         sweep_t = []
         for t in (0, 4096, 8192, 16384, 32768, cap):
-            ms = timed(query(Cp, pp, cp, t), max(K // 2, 3), 1, stream)
+            ms = timed(query(Cp, pp, cp, t), max(K // 2, 10), 1, stream)
             sweep_t.append({"hot_rows": t, "ms": round(ms, 4), "tuples_per_s": F / (ms * 1e-3)})
         result["hot_prefix_sweep"] = sweep_t
         # cold caches: a 512 MB write (twice the memory-side cache) before each query, outside the timed region
         flush = torch.empty(1 << 27, dtype=torch.int32, device=dev)
         cold_ms = []
-        for _ in range(max(K // 2, 3)):
+        for _ in range(max(K // 2, 10)):
             flush.fill_(1)
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
@@ -323,11 +325,11 @@ def main():
             d = W.device_join_inputs(k, N, F, s, dev)
             L = skew.build_skew_layout(d["fact"], N, d["price"], d["category"], in_place=False, ws=bws)
             ms_i = timed(lambda: skew.fk_join_aggregate(d["fact"], d["price"], d["category"], 16, True, hot_rows=0,
-                                                        ws=jws, out=(out_s, out_c)), max(K // 2, 3), 1, stream)
+                                                        ws=jws, out=(out_s, out_c)), max(K // 2, 10), 1, stream)
             ri = out_s.cpu().numpy().copy()
             ms_s = timed(lambda: skew.fk_join_aggregate(L.fact_recoded, L.price, L.category, 16, True,
                                                         hot_rows=t_hot, ws=jws, out=(out_s, out_c)),
-                         max(K // 2, 3), 1, stream)
+                         max(K // 2, 10), 1, stream)
             rs = out_s.cpu().numpy().copy()
             sweep_s.append({"zipf_s": s, "identity_tuples_per_s": F / (ms_i * 1e-3),
                             "skew_tuples_per_s": F / (ms_s * 1e-3), "speedup": ms_i / ms_s,
@@ -425,6 +427,18 @@ def bench_group_by(K, WU, dev, stream):
         res[name] = {"ms": ms, "tuples_per_s": F / (ms * 1e-3),
                      "sum_digest": hashlib.sha256(out[0].cpu().numpy().tobytes() +
                                                   out[1].cpu().numpy().tobytes()).hexdigest()[:16]}
+    # hot-group threshold sweep (Section 4.3's hybrid private/shared aggregation; Section 5.1 sweeps its
+    # threshold): t_g groups privatised in LDS, the rest partitioned (large workspace) or sent to global
+    # atomics (single pass); t_g = 0 is the layout-oblivious method of each form
+    sweep = []
+    for form, ws in (("partitioned", gws), ("single_pass", gws1)):
+        cap = skew.max_hot_groups() if form == "partitioned" else skew.max_hot(skew.SKEW_OP_GROUP_SINGLE_PASS)
+        for t in (0, 1024, 4096, 8192, cap):
+            ms = timed(lambda: skew.group_aggregate(L.fact_recoded, V, M, hot_groups=t, perm=L.perm, ws=ws,
+                                                    out=out), max(K // 2, 10), 1, stream)
+            dg = hashlib.sha256(out[0].cpu().numpy().tobytes() + out[1].cpu().numpy().tobytes()).hexdigest()[:16]
+            sweep.append({"form": form, "hot_groups": t, "ms": round(ms, 4), "tuples_per_s": F / (ms * 1e-3),
+                          "same_result": dg == res["skew"]["sum_digest"]})
     skew.profile_report()
     skew.profile_enable(True)
     for _ in range(3):
@@ -438,6 +452,7 @@ def bench_group_by(K, WU, dev, stream):
             "runs": res, "speedup_vs_identity": res["identity"]["ms"] / ms,
             "speedup_vs_best_identity": min(r["ms"] for n, r in res.items() if n.startswith("identity")) / ms,
             "roofline_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "stages_ms": stages,
+            "hot_group_sweep": sweep,
             "build_s_incl_sync": build_s,
             "layouts_agree": len({r["sum_digest"] for r in res.values()}) == 1}
 
@@ -555,7 +570,7 @@ def bench_serve(seconds, dev):
 
 
 def bench_cache_model(cbr, rank, N, F, dev):
-    """Section 3.4's model for the dimension lookups: 128-byte lines of 32 values, one XCD's 4 MB L2
+    """Section 3.3's model for the dimension lookups: 128-byte lines of 32 values, one XCD's 4 MB L2
     (32768 lines; each XCD sees the whole access distribution) and the 256 MB memory-side cache."""
     import torch
 
@@ -629,40 +644,51 @@ def bench_operators(K, C, price, Cp, pp, perm, N, F, dev, stream):
     return res
 
 
-def cpu_baseline(C, price, cat, rows, gpu_res):
-    """The CPU oracle, as it stands, on the first `rows` fact rows of the identity layout (one thread)."""
+def cpu_baseline(C, price, cat, rows, gpu_res, repeats=3):
+    """The CPU oracle, as it stands, on the first `rows` fact rows of the identity layout: median of `repeats`
+    runs on one thread, then median of `repeats` runs on every host core this process may use, up to the 16
+    cores that one GPU's share of the host grants (contiguous chunks of the column, one per thread; the
+    foreign call releases the interpreter lock; partial sums added in chunk order)."""
+    import concurrent.futures as cf
+
     import numpy as np
 
     import oracle
 
     n = min(rows, C.numel())
-    log(f"cpu oracle on {n} rows")
+    log(f"cpu oracle on {n} rows, {repeats} runs on one thread")
     Ch = C[:n].cpu().numpy()
     ph = price.cpu().numpy()
     ch = cat.cpu().numpy()
-    t = time.perf_counter()
-    s, c = oracle.fk_join_aggregate(Ch, ph, ch, 16, True)
-    dt = time.perf_counter() - t
+    times = []
+    for _ in range(repeats):
+        t = time.perf_counter()
+        s, c = oracle.fk_join_aggregate(Ch, ph, ch, 16, True)
+        times.append(time.perf_counter() - t)
+    dt = float(np.median(times))
     out = {"value": n / dt, "unit": "fact tuples/s", "cores": 1, "kind": "oracle",
-           "sample": f"first {n} of {C.numel()} fact rows, identity layout, same query; {dt:.2f} s on 1 thread",
-           "cpu_model": _cpu_model()}
+           "sample": f"first {n} of {C.numel()} fact rows, identity layout, same query; median of {repeats} runs "
+                     f"on 1 thread: {dt:.2f} s", "runs_s": [round(x, 3) for x in times], "cpu_model": _cpu_model()}
     if gpu_res is not None:
         out["bit_exact_vs_oracle"] = bool((s == gpu_res[0]).all() and (c == gpu_res[1]).all())
-    # the same oracle function on every host core: contiguous chunks of the column, one per thread (the
-    # foreign call releases the interpreter lock), partial sums added in chunk order
-    import concurrent.futures as cf
-
-    cores = min(16, len(os.sched_getaffinity(0)))
+    affinity = len(os.sched_getaffinity(0))
+    cores = min(16, affinity)
+    log(f"cpu oracle on {cores} threads ({affinity} cores in the affinity mask)")
     bounds = np.linspace(0, n, cores + 1).astype(np.int64)
-    t = time.perf_counter()
+    times = []
     with cf.ThreadPoolExecutor(cores) as ex:
-        parts = list(ex.map(lambda i: oracle.fk_join_aggregate(Ch[bounds[i]:bounds[i + 1]], ph, ch, 16, True),
-                            range(cores)))
-    dt = time.perf_counter() - t
+        for _ in range(repeats):
+            t = time.perf_counter()
+            parts = list(ex.map(lambda i: oracle.fk_join_aggregate(Ch[bounds[i]:bounds[i + 1]], ph, ch, 16, True),
+                                range(cores)))
+            times.append(time.perf_counter() - t)
+    dt = float(np.median(times))
     sp = np.sum([p[0] for p in parts], axis=0)
     cp = np.sum([p[1] for p in parts], axis=0)
-    out["all_cores"] = {"value": n / dt, "unit": "fact tuples/s", "cores": cores, "kind": "oracle",
-                        "sample": f"the same {n} rows in {cores} contiguous chunks, one thread each; {dt:.2f} s",
+    out["all_cores"] = {"value": n / dt, "unit": "fact tuples/s", "cores": cores, "affinity_cores": affinity,
+                        "kind": "oracle",
+                        "sample": f"the same {n} rows in {cores} contiguous chunks, one thread each; median of "
+                                  f"{repeats} runs: {dt:.2f} s", "runs_s": [round(x, 3) for x in times],
                         "equals_one_thread": bool((sp == s).all() and (cp == c).all())}
     return out
 

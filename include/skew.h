@@ -237,10 +237,10 @@ int heavy_hitter_counts(const int32_t *ranked_keys, int64_t n_fact, int32_t n_ke
                         void *stream);
 
 /*
- * cache_model_hit_rate - the stack-distance cache model of Section 3.4: the
+ * cache_model_hit_rate - the stack-distance cache model of Section 3.3: the
  * hit rate an LRU cache of cache_lines lines is expected to reach on the
  * dimension lookups of a fact column, for a given layout.  Line frequencies
- * come from the key frequencies (Section 3.4: with the frequency-ordered
+ * come from the key frequencies (Section 3.3: with the frequency-ordered
  * layout the most frequent line holds the v most frequent values); for line
  * i the model finds the number of trials K_i after which S other distinct
  * lines are expected, and sums f_i (1 - (1 - f_i)^K_i).
@@ -364,7 +364,8 @@ int skew_profile_report(char *names, int names_bytes, float *ms, int *calls, int
 int32_t skew_max_hot_rows(int32_t group_by_category);
 int32_t skew_max_hot_groups(void);
 /* op: SKEW_OP_MATERIALIZE (rows), SKEW_OP_SELECT (rows, i.e. bits), SKEW_OP_HEAVY
- * (ranks counted in LDS; ranks in [capacity, k) use global atomics). */
+ * (ranks counted in LDS; ranks in [capacity, k) use global atomics),
+ * SKEW_OP_GROUP_SINGLE_PASS (hot groups of the single-pass group-by). */
 int64_t skew_max_hot(int op);
 
 #ifdef __cplusplus

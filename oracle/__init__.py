@@ -193,13 +193,13 @@ def star_join(P, U, price, category, cust_attr, cust_lt: int):
 
 
 def cache_model(f, cache_lines: int) -> float:
-    """Hit rate of the stack-distance model of Section 3.4 for line frequencies f (summing to 1)."""
+    """Hit rate of the stack-distance model of Section 3.3 for line frequencies f (summing to 1)."""
     f = _c(f, np.float64)
     return float(_load().oracle_cache_model(_p(f), f.size, int(cache_lines)))
 
 
 def line_frequencies(counts_by_key, values_per_line: int):
-    """Access frequency of every cache line of `values_per_line` consecutive keys (Section 3.4)."""
+    """Access frequency of every cache line of `values_per_line` consecutive keys (Section 3.3)."""
     c = np.asarray(counts_by_key, dtype=np.float64)
     n_lines = (c.size + values_per_line - 1) // values_per_line
     pad = np.zeros(n_lines * values_per_line)

@@ -241,7 +241,7 @@ int32_t oracle_heavy_hitters(const int32_t *G, int64_t n_fact, int32_t n_keys, i
 }
 
 /*
- * Stack-distance cache model (Section 3.4), as the paper states it.  f[0..L)
+ * Stack-distance cache model (Section 3.3), as the paper states it.  f[0..L)
  * are the access frequencies of the cache lines (summing to 1) and the LRU
  * cache holds S lines.  For line i the next reference is geometric with
  * success probability f_i; after k trials every other line j is expected

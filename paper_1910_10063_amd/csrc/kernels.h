@@ -110,7 +110,7 @@ hipError_t launch_select(const int32_t *keys, int64_t n_fact, const int32_t *col
 hipError_t launch_heavy(const int32_t *keys, int64_t n_fact, int32_t n_keys, int32_t k, const int32_t *perm,
                         int32_t *out_keys, int64_t *out_count, int32_t *flag, const DeviceInfo &dev, hipStream_t s);
 
-// ---- stack-distance cache model (Section 3.4) ----
+// ---- stack-distance cache model (Section 3.3) ----
 size_t model_workspace_bytes(int32_t n_keys, int32_t values_per_line);
 hipError_t launch_cache_model(const uint32_t *counts_by_rank, int32_t n_keys, const int32_t *rank,
                               int32_t values_per_line, int64_t cache_lines, void *ws, double *out_hit,

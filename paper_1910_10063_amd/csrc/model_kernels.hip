@@ -1,5 +1,5 @@
-// Stack-distance cache model of Section 3.4 on the device: the access
-// frequency of every cache line for a layout (Section 3.4: with the
+// Stack-distance cache model of Section 3.3 on the device: the access
+// frequency of every cache line for a layout (Section 3.3: with the
 // frequency-ordered layout a line's frequency is the sum of the v largest
 // value frequencies; with the identity layout the v keys stored in it), the
 // lines sorted by frequency, and one thread per line evaluating the model with

@@ -675,6 +675,8 @@ int64_t skew_max_hot(int op) {
       return skew::select_max_hot_rows(dev);
     case SKEW_OP_HEAVY:
       return skew::heavy_max_lds_ranks(dev);
+    case SKEW_OP_GROUP_SINGLE_PASS:
+      return skew::group_max_hot_groups(dev);
     default:
       return fail(SKEW_EINVAL, "op %d has no hot prefix of its own", op);
   }

@@ -17,11 +17,13 @@ resident fact table (the grouped aggregation Q3 of Section 1).  The server works
   (drift), it rebuilds the layout on a side stream and switches to the rebuilt layout when it is ready.
 
 Every step of every request runs in the library's HIP kernels (paper_1910_10063_amd.skew).  This module
-schedules, and it measures latency with wall-clock times at arrival and at completion.
+schedules, and it measures latency with wall-clock times at arrival and at completion.  A request may bring
+its own device output buffers; the aggregation then writes its result there and nothing is copied.
 """
 from __future__ import annotations
 
 import math
+import threading
 import time
 from dataclasses import dataclass
 
@@ -41,7 +43,9 @@ class Request:
     layout: str = ""        # "skew" or "identity"
     admitted: float = math.nan
     done: float = math.nan
-    digest: tuple[int, int] | None = None
+    # int64 SUM and COUNT outputs [n_groups] on the device, written by the request's aggregation; None: the
+    # slot's own buffers, overwritten by the slot's next request
+    out: tuple[torch.Tensor, torch.Tensor] | None = None
 
 
 @dataclass
@@ -61,7 +65,6 @@ class Slot:
     stream: torch.cuda.Stream
     ws: torch.Tensor
     out: tuple[torch.Tensor, torch.Tensor]
-    digest: torch.Tensor
     done: torch.cuda.Event
     req: Request | None = None
 
@@ -120,11 +123,7 @@ class Server:
             ws = skew.workspace(skew.SKEW_OP_GROUP, max_rows, self.n_groups, self.device)
             out = (torch.empty(self.n_groups, dtype=torch.int64, device=self.device),
                    torch.empty(self.n_groups, dtype=torch.int64, device=self.device))
-            self.slots.append(Slot(torch.cuda.Stream(self.device), ws, out,
-                                   torch.zeros(2, dtype=torch.int64, device=self.device),
-                                   torch.cuda.Event(enable_timing=False)))
-        self.weights = (torch.arange(self.n_groups, device=self.device, dtype=torch.int64) * 2 + 1,
-                        torch.arange(self.n_groups, device=self.device, dtype=torch.int64) + 1)
+            self.slots.append(Slot(torch.cuda.Stream(self.device), ws, out, torch.cuda.Event(enable_timing=False)))
         self.side = torch.cuda.Stream(self.device)  # layout rebuilds
         self.build_ws = None
         self.current = table
@@ -139,19 +138,21 @@ class Server:
 
     # ---- layout maintenance
     def build_layout(self, table: TableVersion, stream) -> None:
-        """Frequency-ordered layout of `table` on `stream` (Section 3.1)."""
+        """Frequency-ordered layout of `table` on `stream` (Section 3.1).  The build workspace and the layout's
+        arrays are allocated on `stream`, the stream that uses them."""
         n = table.keys.numel()
         need = skew.workspace_bytes(skew.SKEW_OP_BUILD, n, self.n_groups)
-        if self.build_ws is None or self.build_ws.numel() < need:
-            self.build_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         with torch.cuda.stream(stream):
+            if self.build_ws is None or self.build_ws.numel() < need:
+                self.build_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
             table.layout = skew.build_skew_layout(table.keys, self.n_groups, ws=self.build_ws)
 
     def measure_hot_share(self, table: TableVersion) -> None:
-        """Share of the table's rows that its own layout sends to the hot prefix (after its build)."""
+        """Share of the table's rows that its own layout sends to the hot prefix (after its build): the
+        frequencies of the hot ranks, copied to the host and added there."""
         t = min(skew.max_hot_groups(), self.n_groups)
-        table.hot_share = float(table.layout.counts_by_rank[:t].to(torch.int64).sum().item()) / max(
-            table.keys.numel(), 1)
+        cnt = table.layout.counts_by_rank[:t].cpu().numpy().astype(np.uint32).astype(np.int64)
+        table.hot_share = float(cnt.sum()) / max(table.keys.numel(), 1)
 
     def hot_share_under(self, layout_table: TableVersion, table: TableVersion) -> float:
         """Share of a sample of `table`'s rows whose rank under layout_table's layout is below the hot
@@ -175,16 +176,31 @@ class Server:
             self.events.append({"t": self.now(), "event": "drift_check", "old_share": old.hot_share,
                                 "new_share": share, "drift": drift})
         if drift:
-            ev = torch.cuda.Event(enable_timing=True)
-            ev0 = torch.cuda.Event(enable_timing=True)
-            ev0.record(self.side)
-            self.build_layout(table, self.side)
-            ev.record(self.side)
-            self.rebuild = {"table": table, "event": ev, "start": ev0, "t": self.now()}
+            # The build waits for its histogram (a range check) before it enqueues the rest, so it is issued
+            # from a worker thread: admission and harvesting go on meanwhile.
+            r = {"table": table, "event": torch.cuda.Event(enable_timing=True),
+                 "start": torch.cuda.Event(enable_timing=True), "t": self.now(), "error": None}
+
+            def work():
+                try:
+                    r["start"].record(self.side)
+                    self.build_layout(table, self.side)
+                    r["event"].record(self.side)
+                except Exception as e:  # reported by poll_rebuild on the serving thread
+                    r["error"] = e
+
+            r["thread"] = threading.Thread(target=work, daemon=True)
+            r["thread"].start()
+            self.rebuild = r
 
     def poll_rebuild(self) -> None:
-        if self.rebuild is not None and self.rebuild["event"].query():
-            r = self.rebuild
+        r = self.rebuild
+        if r is None or r["thread"].is_alive():
+            return
+        if r["error"] is not None:
+            self.rebuild = None
+            raise r["error"]
+        if r["event"].query():
             self.measure_hot_share(r["table"])
             self.serving_layout = r["table"]
             self.events.append({"t": self.now(), "event": "layout_ready", "version": r["table"].version,
@@ -200,23 +216,20 @@ class Server:
         req.layout = "skew" if use_skew else "identity"
         req.admitted = self.now()
         a, n = req.start, req.rows
+        out = req.out if req.out is not None else slot.out
         with torch.cuda.stream(slot.stream):
             if use_skew:
                 skew.group_aggregate(tab.layout.fact_recoded[a:a + n], tab.vals[a:a + n], self.n_groups,
-                                     hot_groups=skew.SKEW_HOT_AUTO, perm=tab.layout.perm, ws=slot.ws, out=slot.out)
+                                     hot_groups=skew.SKEW_HOT_AUTO, perm=tab.layout.perm, ws=slot.ws, out=out)
             else:
                 skew.group_aggregate(tab.keys[a:a + n], tab.vals[a:a + n], self.n_groups, hot_groups=0,
-                                     ws=slot.ws, out=slot.out)
-            # result digest on the device (int64 arithmetic, order-independent)
-            slot.digest[0] = (slot.out[0] * self.weights[0]).sum()
-            slot.digest[1] = (slot.out[1] * self.weights[1]).sum()
+                                     ws=slot.ws, out=out)
             slot.done.record(slot.stream)
         slot.req = req
 
     def harvest(self, slot: Slot) -> Request:
+        """The slot's stream has passed its done event: the request's outputs are complete."""
         req = slot.req
-        d = slot.digest.cpu()  # the slot's stream is complete: done.query() was true
-        req.digest = (int(d[0]), int(d[1]))
         req.done = self.now()
         slot.req = None
         return req
@@ -247,6 +260,9 @@ class Server:
             if idle_sleep and not pending:
                 time.sleep(idle_sleep)
         torch.cuda.synchronize(self.device)
+        if self.rebuild is not None:
+            self.rebuild["thread"].join()
+            torch.cuda.synchronize(self.device)
         self.poll_rebuild()
         return finished
 

@@ -286,7 +286,7 @@ def heavy_hitter_counts(ranked_keys: torch.Tensor, n_keys: int, k: int, perm: to
 
 def cache_model_hit_rate(counts_by_rank: torch.Tensor, cache_lines: int, values_per_line: int = 32,
                          rank: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> float:
-    """Hit rate of the stack-distance model (Section 3.4); rank=None: frequency-ordered layout."""
+    """Hit rate of the stack-distance model (Section 3.3); rank=None: frequency-ordered layout."""
     lib = load_library()
     _need(counts_by_rank, torch.int32, "counts_by_rank")
     if rank is not None:

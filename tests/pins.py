@@ -334,7 +334,7 @@ def pin_heavy_hitters(orc, seeds=range(10)):
 
 
 # ---------------------------------------------------------------------------
-# Stack-distance cache model (Section 3.4)
+# Stack-distance cache model (Section 3.3)
 # ---------------------------------------------------------------------------
 def lru_hit_rate(f, S, n, seed):
     """Exact LRU cache of S lines fed n i.i.d. accesses drawn from f (hits after a warm-up fifth)."""

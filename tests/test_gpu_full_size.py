@@ -6,8 +6,11 @@ generated on the device from the same seeds as the bench; the layout is built,
 and the query runs with the library's default hot prefix (SKEW_HOT_AUTO) on
 the frequency-ordered layout and with no prefix on the identity layout.  The
 oracle computes every output from the host copy of the identity-layout
-columns; the GPU results must equal it exactly.  The layout itself is checked
-through properties that hold at any size.
+columns; the GPU results must equal it exactly.  The layouts of the join and
+group-by columns are compared with the oracle's element by element: key
+counts by rank, permutation, rank, the permuted dimension columns and the
+whole recoded column (in chunks); the layouts of the other workloads through
+properties that hold at any size.
 """
 import sys
 
@@ -44,23 +47,41 @@ def check_layout_properties(L, n_keys, n_fact):
     assert (perm[ties] < perm[ties + 1]).all(), "equal frequencies in ascending key order"
 
 
+def check_layout_vs_oracle(L, keys_h, n_keys, price_h=None, cat_h=None, chunk=1 << 27):
+    cnt, inv = oracle.key_counts(keys_h, n_keys)
+    assert inv == 0
+    perm, rank = oracle.permutation_index(cnt)
+    np.testing.assert_array_equal(host(L.perm), perm, err_msg="perm")
+    np.testing.assert_array_equal(host(L.rank), rank, err_msg="rank")
+    np.testing.assert_array_equal(host(L.counts_by_rank).astype(np.uint32).astype(np.int64), cnt[perm],
+                                  err_msg="counts by rank")
+    if price_h is not None:
+        np.testing.assert_array_equal(host(L.price), oracle.permute_dim(price_h, perm), err_msg="permuted price")
+    if cat_h is not None:
+        np.testing.assert_array_equal(host(L.category), oracle.permute_dim(cat_h, perm), err_msg="permuted category")
+    for a in range(0, keys_h.size, chunk):
+        b = min(a + chunk, keys_h.size)
+        np.testing.assert_array_equal(host(L.fact_recoded[a:b]), oracle.recode(keys_h[a:b], rank),
+                                      err_msg=f"recoded keys [{a}, {b})")
+
+
 def test_join_full_size():
     N, F, S = 10_000_000, 1_000_000_000, 1.0
     say(f"join full size N={N} F={F} s={S}")
     d = W.device_join_inputs(2, N, F, S, DEV)
     L = skew.build_skew_layout(d["fact"], N, d["price"], d["category"])
     check_layout_properties(L, N, F)
-    # sampled recode: C'[j] = rank[C[j]]
-    idx = torch.from_numpy(np.random.default_rng(1).integers(0, F, 1_000_000)).to(DEV)
-    assert torch.equal(L.fact_recoded[idx], L.rank[d["fact"][idx].long()])
-    es, ec = oracle.fk_join_aggregate(host(d["fact"]), host(d["price"]), host(d["category"]), 16, True)
+    fact_h, price_h, cat_h = host(d["fact"]), host(d["price"]), host(d["category"])
+    say("join full size: layout vs oracle")
+    check_layout_vs_oracle(L, fact_h, N, price_h, cat_h)
+    es, ec = oracle.fk_join_aggregate(fact_h, price_h, cat_h, 16, True)
     ws = skew.workspace(skew.SKEW_OP_JOIN, F, N, DEV)
     s, c = skew.fk_join_aggregate(L.fact_recoded, L.price, L.category, 16, True, hot_rows=skew.SKEW_HOT_AUTO, ws=ws)
     assert (host(s) == es).all() and (host(c) == ec).all(), "skew layout"
     s, c = skew.fk_join_aggregate(d["fact"], d["price"], d["category"], 16, True, hot_rows=0, ws=ws)
     assert (host(s) == es).all() and (host(c) == ec).all(), "identity layout"
     assert skew.query_status(ws) == skew.SKEW_OK
-    del d, L, ws, idx
+    del d, L, ws, fact_h
     torch.cuda.empty_cache()
 
 
@@ -70,7 +91,10 @@ def test_group_by_full_size():
     g = W.device_group_inputs(3, M, F, S, device=DEV)
     L = skew.build_skew_layout(g["keys"], M)
     check_layout_properties(L, M, F)
-    es, ec, inv = oracle.group_aggregate(host(g["keys"]), host(g["vals"]), M)
+    keys_h = host(g["keys"])
+    say("group-by full size: layout vs oracle")
+    check_layout_vs_oracle(L, keys_h, M)
+    es, ec, inv = oracle.group_aggregate(keys_h, host(g["vals"]), M)
     assert inv == 0
     ws = skew.workspace(skew.SKEW_OP_GROUP, F, M, DEV)
     s, c = skew.group_aggregate(L.fact_recoded, g["vals"], M, hot_groups=skew.SKEW_HOT_AUTO, perm=L.perm, ws=ws)

@@ -1,4 +1,4 @@
-"""The stack-distance cache model of Section 3.4 on the device against the oracle.
+"""The stack-distance cache model of Section 3.3 on the device against the oracle.
 
 Both evaluate the same model in fp64 (the device with sorted line counts and
 prefix sums, the oracle with direct sums); the tolerance covers a search that

@@ -1,11 +1,13 @@
 """The serving loop on the GPU: continuous batching gives every request the same answer as alone.
 
-Requests arrive at their times, up to six run concurrently on their slots'
-streams; each result (a digest of the int64 SUM and COUNT of 1e5 groups)
-equals the result of the same request served alone, and the oracle's for
-sampled requests.  A new table version with re-permuted popularity is served
-on the identity layout at once, detected as drift, rebuilt on a side stream,
-and served on its own layout afterwards, with unchanged answers.
+Requests arrive at their times and up to six run concurrently on their
+slots' streams.  Every request brings its own device output buffers, so its
+int64 SUM and COUNT arrays over all 1e5 groups are kept whole: each one is
+compared element by element with the same request served alone (one slot)
+and with the oracle.  A new table version with re-permuted popularity is
+served on the identity layout at once, detected as drift, rebuilt on a side
+stream, and served on its own layout afterwards; every answer, before and
+after the switch, is compared with the oracle element by element.
 """
 import sys
 
@@ -14,7 +16,7 @@ import pytest
 import torch
 
 import oracle
-from paper_1910_10063_amd import serving, skew
+from paper_1910_10063_amd import serving
 from paper_1910_10063_amd import workload as W
 
 pytestmark = pytest.mark.gpu
@@ -25,16 +27,6 @@ M, F = 100_000, 20_000_000
 def say(msg):
     print(f"[case] {msg}", flush=True)
     sys.stdout.flush()
-
-
-def digest(s, c):
-    w0 = np.arange(M, dtype=object) * 2 + 1
-    w1 = np.arange(M, dtype=object) + 1
-
-    def wrap(v):
-        return ((int(v) + 2**63) % 2**64) - 2**63
-
-    return wrap(sum(s.astype(object) * w0)), wrap(sum(c.astype(object) * w1))
 
 
 def version(v, k):
@@ -52,7 +44,12 @@ def tables():
 
 def requests(seed):
     arr = serving.poisson_arrivals(200.0, 0.4, seed)
-    return serving.make_requests(arr, F, 10_000, 4_000_000, seed)
+    reqs = serving.make_requests(arr, F, 10_000, 4_000_000, seed)
+    for r in reqs:  # the request's own outputs, filled with a value no aggregate takes
+        r.out = (torch.full((M,), -7, dtype=torch.int64, device=DEV), torch.full((M,), -7, dtype=torch.int64,
+                                                                                   device=DEV))
+    torch.cuda.synchronize()  # the fills are done before any slot stream writes
+    return reqs
 
 
 def run(tables, slots, versions=None, seed=5):
@@ -60,39 +57,55 @@ def run(tables, slots, versions=None, seed=5):
     srv = serving.Server(t1, slots, 4_000_000)
     serving.start_layout(srv, t1)
     done = srv.run(requests(seed), versions)
+    torch.cuda.synchronize()
     return srv, {r.rid: r for r in done}
 
 
+def arrays(r):
+    return r.out[0].cpu().numpy(), r.out[1].cpu().numpy()
+
+
+def expected(h, r):
+    s, c, inv = oracle.group_aggregate(h["keys"][r.start:r.start + r.rows], h["vals"][r.start:r.start + r.rows], M)
+    assert inv == 0
+    return s, c
+
+
 def test_alone_equals_mix_and_oracle(tables):
-    say("serving: one slot vs six slots")
+    say("serving: one slot vs six slots, every request element-wise")
     _, alone = run(tables, 1)
     _, mix = run(tables, 6)
     assert alone.keys() == mix.keys() and len(alone) > 20
-    for rid, r in mix.items():
-        assert r.digest == alone[rid].digest, rid
-        assert r.layout == "skew"
     h = tables["h1"]
-    for rid in sorted(alone)[:: max(1, len(alone) // 6)]:
-        r = alone[rid]
-        s, c, inv = oracle.group_aggregate(h["keys"][r.start:r.start + r.rows], h["vals"][r.start:r.start + r.rows], M)
-        assert inv == 0 and digest(s, c) == r.digest, rid
+    for rid in sorted(mix):
+        r, a = mix[rid], alone[rid]
+        assert r.layout == "skew" and a.layout == "skew"
+        ms, mc = arrays(r)
+        as_, ac = arrays(a)
+        np.testing.assert_array_equal(ms, as_, err_msg=f"request {rid}: SUM alone vs in the mix")
+        np.testing.assert_array_equal(mc, ac, err_msg=f"request {rid}: COUNT alone vs in the mix")
+        es, ec = expected(h, r)
+        np.testing.assert_array_equal(ms, es, err_msg=f"request {rid}: SUM vs oracle")
+        np.testing.assert_array_equal(mc, ec, err_msg=f"request {rid}: COUNT vs oracle")
     # overlap: some request was admitted before an earlier one finished
     rs = sorted(mix.values(), key=lambda r: r.admitted)
     assert any(b.admitted < a.done for a, b in zip(rs, rs[1:]))
 
 
 def test_drift_rebuild_keeps_answers(tables):
-    say("serving: new version at 0.2 s, drift detection, rebuild")
+    say("serving: new version at 0.2 s, drift detection, rebuild; every request vs the oracle")
     srv, done = run(tables, 4, versions=[(0.2, tables["t2"])], seed=7)
     ev = [e["event"] for e in srv.events]
     assert "version" in ev and "layout_ready" in ev
     chk = [e for e in srv.events if e["event"] == "drift_check"][0]
     assert chk["drift"] and chk["new_share"] < 0.8 * chk["old_share"]
     assert {r.version for r in done.values()} == {1, 2}
-    for rid in sorted(done)[::3]:
+    for rid in sorted(done):
         r = done[rid]
         h = tables["h1"] if r.version == 1 else tables["h2"]
-        s, c, _ = oracle.group_aggregate(h["keys"][r.start:r.start + r.rows], h["vals"][r.start:r.start + r.rows], M)
-        assert digest(s, c) == r.digest, (rid, r.version, r.layout)
+        gs, gc = arrays(r)
+        es, ec = expected(h, r)
+        np.testing.assert_array_equal(gs, es, err_msg=f"request {rid} (version {r.version}, {r.layout}): SUM")
+        np.testing.assert_array_equal(gc, ec, err_msg=f"request {rid} (version {r.version}, {r.layout}): COUNT")
     v2 = [r for r in done.values() if r.version == 2]
     assert any(r.layout == "skew" for r in v2)
