@@ -141,6 +141,25 @@ int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *d
                       size_t workspace_bytes, void *stream);
 
 /*
+ * fk_join_aggregate_noalloc - fk_join_aggregate for callers that cannot
+ * allocate device memory or pass a workspace: code under HIP graph capture,
+ * serving loops and harnesses that forbid allocation.  Same arguments and
+ * result as fk_join_aggregate without the workspace; it runs the single-pass
+ * form.  Its scratch (the error flag and one packed 4-byte word per dimension
+ * row) is a fixed array inside the library, one per device, held until the
+ * process ends: n_rows above SKEW_NOALLOC_MAX_ROWS returns SKEW_EINVAL.  The
+ * call allocates nothing.  Every call on a device shares that device's array,
+ * which keeps the last call's contents (each call rewrites what it reads):
+ * calls that overlap on one device, on different streams or threads, race,
+ * and the caller must order them.  With SKEW_CHECK=1 the call waits and
+ * returns SKEW_ERANGE when a key was outside [0, n_rows).
+ */
+#define SKEW_NOALLOC_MAX_ROWS (1 << 24) /* 64 MiB of words + 256 bytes per device */
+int fk_join_aggregate_noalloc(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_price,
+                              const int8_t *dim_category, int32_t n_rows, int32_t cat_lt, int32_t group_by_category,
+                              int32_t hot_rows, int64_t *out_sum, int64_t *out_count, void *stream);
+
+/*
  * group_aggregate - grouped SUM and COUNT (Q3 of Section 1) with hybrid
  * private/shared aggregation (Section 4.3) and per-lane copies of the hottest
  * groups (Section 4.2.2).

@@ -147,6 +147,36 @@ skew::DeviceInfo part_device(const skew::DeviceInfo &dev) {
   return d;
 }
 
+// Scratch of fk_join_aggregate_noalloc, for callers that cannot allocate: the
+// error flag (first kFlagBytes) and the packed dimension words of up to
+// SKEW_NOALLOC_MAX_ROWS rows.  Every device the library runs on holds its own
+// copy until the process ends.  In host code `scratch` is a host-side stand-in:
+// its device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = skew::kFlagBytes + (size_t)SKEW_NOALLOC_MAX_ROWS * 4;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::once_flag g_scratch_once[kMaxDevices];
+void *g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// Device address of this device's scratch; call with the device current.
+int scratch_address(int dev, char **out) {
+  std::call_once(g_scratch_once[dev], [dev] {
+    void *p = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? p : nullptr;
+  });
+  if (g_scratch_err[dev] != hipSuccess) return hip_fail(g_scratch_err[dev], "address of the library's scratch");
+  if (!g_scratch_ptr[dev] || ((uintptr_t)g_scratch_ptr[dev] & 255u))
+    return fail(SKEW_EHIP, "the library's scratch has no 256-byte aligned device address");
+  *out = (char *)g_scratch_ptr[dev];
+  return SKEW_OK;
+}
+
 int read_flag(const void *workspace, hipStream_t s) {
   int32_t flag = 0;
   hipError_t e = hipMemcpyAsync(&flag, workspace, sizeof flag, hipMemcpyDeviceToHost, s);
@@ -292,29 +322,42 @@ int build_skew_layout(const int32_t *fact_keys, int64_t n_fact, int32_t n_keys, 
   return ok();
 }
 
-int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_price,
-                      const int8_t *dim_category, int32_t n_rows, int32_t cat_lt, int32_t group_by_category,
-                      int32_t hot_rows, int64_t *out_sum, int64_t *out_count, void *workspace,
-                      size_t workspace_bytes, void *stream) {
+namespace {
+
+// Argument checks shared by the two join entry points (everything but the workspace).
+int join_check(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_price, const int8_t *dim_category,
+               int32_t n_rows, int32_t group_by_category, int32_t hot_rows, const int64_t *out_sum,
+               const int64_t *out_count) {
   if (n_fact < 0) return fail(SKEW_EINVAL, "n_fact must be >= 0");
   if (n_rows < 1) return fail(SKEW_EINVAL, "n_rows must be >= 1");
   if (n_fact > 0 && !fact_keys) return fail(SKEW_EINVAL, "fact_keys is NULL");
   if (!dim_price || !dim_category) return fail(SKEW_EINVAL, "dimension columns are required");
   if (!out_sum || !out_count) return fail(SKEW_EINVAL, "outputs are required");
-  if (!workspace) return fail(SKEW_EINVAL, "workspace is NULL");
   if (group_by_category != 0 && group_by_category != 1) return fail(SKEW_EINVAL, "group_by_category must be 0 or 1");
   if (hot_rows < SKEW_HOT_AUTO) return fail(SKEW_EINVAL, "hot_rows must be >= 0 or SKEW_HOT_AUTO");
   if (!aligned4(fact_keys) || !aligned4(dim_price) || !aligned4(out_sum) || !aligned4(out_count))
     return fail(SKEW_EINVAL, "32/64-bit arrays must be 4-byte aligned");
   if (((uintptr_t)out_sum & 7u) || ((uintptr_t)out_count & 7u))
     return fail(SKEW_EINVAL, "outputs must be 8-byte aligned");
+  return SKEW_OK;
+}
+
+}  // namespace
+
+int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_price,
+                      const int8_t *dim_category, int32_t n_rows, int32_t cat_lt, int32_t group_by_category,
+                      int32_t hot_rows, int64_t *out_sum, int64_t *out_count, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+  if (int rc = join_check(fact_keys, n_fact, dim_price, dim_category, n_rows, group_by_category, hot_rows, out_sum,
+                          out_count))
+    return rc;
+  if (!workspace) return fail(SKEW_EINVAL, "workspace is NULL");
   if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
   const size_t need = join_ws(n_rows);
   if (workspace_bytes < need) return fail(SKEW_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
 
   skew::DeviceInfo dev;
   if (int rc = device_info(&dev)) return rc;
-  const int groups = group_by_category ? 16 : 1;
   const hipStream_t s = (hipStream_t)stream;
   char *ws = (char *)workspace;
   void *part = workspace_bytes > need ? (void *)(ws + need) : nullptr;
@@ -324,6 +367,30 @@ int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *d
                                          part ? workspace_bytes - need : 0, part_device(dev), s);
   if (e != hipSuccess) return hip_fail(e, "join launch");
   if (check_enabled()) return read_flag(workspace, s);
+  return ok();
+}
+
+int fk_join_aggregate_noalloc(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_price,
+                              const int8_t *dim_category, int32_t n_rows, int32_t cat_lt, int32_t group_by_category,
+                              int32_t hot_rows, int64_t *out_sum, int64_t *out_count, void *stream) {
+  if (int rc = join_check(fact_keys, n_fact, dim_price, dim_category, n_rows, group_by_category, hot_rows, out_sum,
+                          out_count))
+    return rc;
+  if (n_rows > SKEW_NOALLOC_MAX_ROWS)
+    return fail(SKEW_EINVAL, "n_rows %d exceeds the %d rows the library's fixed scratch holds", n_rows,
+                SKEW_NOALLOC_MAX_ROWS);
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  char *ws = nullptr;
+  if (int rc = scratch_address(dev.device, &ws)) return rc;
+  const hipStream_t s = (hipStream_t)stream;
+  // The pack kernel clears the flag and the outputs and rewrites every word the query reads.
+  const hipError_t e = skew::launch_join(fact_keys, n_fact, dim_price, dim_category, n_rows, cat_lt,
+                                         group_by_category, hot_rows, out_sum, out_count,
+                                         (uint32_t *)(ws + skew::kFlagBytes), (int32_t *)ws, nullptr, 0,
+                                         part_device(dev), s);
+  if (e != hipSuccess) return hip_fail(e, "join launch");
+  if (check_enabled()) return read_flag(ws, s);
   return ok();
 }
 

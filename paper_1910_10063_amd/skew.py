@@ -40,7 +40,8 @@ SKEW_HOT_NONE = -2
 EXPORTED = ("skew_last_error", "skew_workspace_bytes", "build_skew_layout", "fk_join_aggregate", "group_aggregate",
             "skew_query_status", "skew_profile_enable", "skew_profile_report", "skew_max_hot_rows",
             "skew_max_hot_groups", "materialize_column", "select_fact_rows", "heavy_hitter_counts", "skew_max_hot",
-            "cache_model_hit_rate", "star_join_batch", "star_join_autotune", "stream_probe")
+            "cache_model_hit_rate", "star_join_batch", "star_join_autotune", "stream_probe",
+            "fk_join_aggregate_noalloc")
 
 
 class StarTuning(ctypes.Structure):
@@ -75,6 +76,8 @@ def load_library(path: str = LIB_PATH):
     lib.build_skew_layout.restype = ctypes.c_int
     lib.fk_join_aggregate.argtypes = [P, I64, P, P, I32, I32, I32, I32, P, P, P, SZ, P]
     lib.fk_join_aggregate.restype = ctypes.c_int
+    lib.fk_join_aggregate_noalloc.argtypes = [P, I64, P, P, I32, I32, I32, I32, P, P, P]
+    lib.fk_join_aggregate_noalloc.restype = ctypes.c_int
     lib.group_aggregate.argtypes = [P, P, I64, I32, I32, P, P, P, P, SZ, P]
     lib.group_aggregate.restype = ctypes.c_int
     lib.skew_query_status.argtypes = [P, SZ, P]
@@ -205,6 +208,26 @@ def fk_join_aggregate(fact_keys: torch.Tensor, price: torch.Tensor, category: to
     _check(lib.fk_join_aggregate(_ptr(fact_keys), fact_keys.numel(), _ptr(price), _ptr(category), price.numel(),
                                  int(cat_lt), 1 if group_by_category else 0, int(hot_rows), _ptr(out[0]),
                                  _ptr(out[1]), _ptr(ws), ws.numel(), _stream(dev)))
+    return out
+
+
+SKEW_NOALLOC_MAX_ROWS = 1 << 24
+
+
+def fk_join_aggregate_noalloc(fact_keys: torch.Tensor, price: torch.Tensor, category: torch.Tensor, cat_lt: int,
+                              group_by_category: bool, out: tuple[torch.Tensor, torch.Tensor],
+                              hot_rows: int = SKEW_HOT_AUTO):
+    """fk_join_aggregate without a workspace: the library's fixed per-device scratch (single pass, at most
+    SKEW_NOALLOC_MAX_ROWS dimension rows).  The caller passes the int64 outputs [1] or [16]."""
+    lib = load_library()
+    _need(fact_keys, torch.int32, "fact_keys")
+    _need(price, torch.int32, "price")
+    _need(category, torch.int8, "category")
+    if price.numel() != category.numel():
+        raise ValueError("price and category must have the same length")
+    _check(lib.fk_join_aggregate_noalloc(_ptr(fact_keys), fact_keys.numel(), _ptr(price), _ptr(category),
+                                         price.numel(), int(cat_lt), 1 if group_by_category else 0, int(hot_rows),
+                                         _ptr(out[0]), _ptr(out[1]), _stream(fact_keys.device)))
     return out
 
 

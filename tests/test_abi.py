@@ -256,3 +256,24 @@ def test_star_workspace_holds_the_customer_bitmaps(lib):
     # below 2^20 customers the bitmap is as long as the dimension
     d = lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 9, 100_000) - lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 1, 100_000)
     assert 8 * 100_000 // 8 <= d < 8 * 100_000 // 8 + 2048
+
+
+def _join_noalloc(lib, **kw):
+    a = dict(keys=A, n=10, price=A2, cat=A, rows=100, lt=4, by=1, hot=0, s=A, c=A2)
+    a.update(kw)
+    return lib.fk_join_aggregate_noalloc(a["keys"], a["n"], a["price"], a["cat"], a["rows"], a["lt"], a["by"],
+                                         a["hot"], a["s"], a["c"], S)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=-1), skew.SKEW_EINVAL),
+    (dict(rows=0), skew.SKEW_EINVAL),
+    (dict(rows=skew.SKEW_NOALLOC_MAX_ROWS + 1), skew.SKEW_EINVAL),  # larger than the library's scratch
+    (dict(keys=NULL), skew.SKEW_EINVAL),
+    (dict(keys=MIS), skew.SKEW_EINVAL),
+    (dict(by=2), skew.SKEW_EINVAL),
+    (dict(hot=-3), skew.SKEW_EINVAL),
+    (dict(s=ctypes.c_void_p(0x10004)), skew.SKEW_EINVAL),
+])
+def test_join_noalloc_rejects(lib, kw, code):
+    assert _join_noalloc(lib, **kw) == code
