@@ -232,7 +232,7 @@ def main():
     # beside it, the dominant kernel on its own share: the keys one launch streams, 4 B each.
     dom = max(stages_skew, key=lambda k: stages_skew[k]["ms"])
     launches = stages_skew[dom]["launches"]
-    hot_used = min(skew.max_hot_rows(True), N) if t_hot < 0 else min(t_hot, N)
+    hot_used = skew.join_hot_rows(F, N, True, t_hot, ws=jws)
     cold = int(cbr[hot_used:].to(torch.int64).sum().item())  # fact keys at or above the threshold
     keys_per_launch = F / launches
     dom_bytes = {"join_split": 4.0 * keys_per_launch, "join_single_pass": 4.0 * keys_per_launch,
@@ -297,12 +297,23 @@ def main():
         del single_ws
     if not args.no_extras:
         # hot-prefix sweep, up to the LDS capacity (a larger t is clamped to it)
-        cap = skew.max_hot_rows(True)
         sweep_t = []
-        for t in (0, 4096, 8192, 16384, 32768, cap):
+        for t in (0, 4096, 8192, 16384, 32768, skew.SKEW_HOT_AUTO):
             ms = timed(query(Cp, pp, cp, t), max(K // 2, 10), 1, stream)
-            sweep_t.append({"hot_rows": t, "ms": round(ms, 4), "tuples_per_s": F / (ms * 1e-3)})
+            used = skew.join_hot_rows(F, N, True, t, ws=jws)
+            sweep_t.append({"hot_rows": t, "hot_rows_used": used, "ms": round(ms, 4), "tuples_per_s": F / (ms * 1e-3),
+                            "cold_share": float(cbr[used:].to(torch.int64).sum().item()) / F})
         result["hot_prefix_sweep"] = sweep_t
+        # the library's threshold prior (frequencies of the layout, the stack-distance model of the cold lookups)
+        # beside the measured best of the sweep
+        ch = skew.join_choose(cbr, F, True)
+        ws_ch = jws if ch["partitioned"] else skew.workspace(skew.SKEW_OP_JOIN_SINGLE_PASS, F, N, dev)
+        ms_ch = timed(query(Cp, pp, cp, ch["hot_rows"], ws_ch), max(K // 2, 10), 1, stream)
+        best = min(sweep_t, key=lambda r: r["ms"])
+        result["model_choice"] = dict(ch, ms=round(ms_ch, 4), tuples_per_s=F / (ms_ch * 1e-3),
+                                      sweep_best={"hot_rows": best["hot_rows"], "ms": best["ms"]},
+                                      ms_over_sweep_best=round(ms_ch / best["ms"], 4))
+        del ws_ch
         # cold caches: a 512 MB write (twice the memory-side cache) before each query, outside the timed region
         flush = torch.empty(1 << 27, dtype=torch.int32, device=dev)
         cold_ms = []
@@ -331,9 +342,19 @@ def main():
                                                         hot_rows=t_hot, ws=jws, out=(out_s, out_c)),
                          max(K // 2, 10), 1, stream)
             rs = out_s.cpu().numpy().copy()
+            ch = skew.join_choose(L.counts_by_rank, F, True)
+            ws_ch = jws if ch["partitioned"] else skew.workspace(skew.SKEW_OP_JOIN_SINGLE_PASS, F, N, dev)
+            ms_c = timed(lambda: skew.fk_join_aggregate(L.fact_recoded, L.price, L.category, 16, True,
+                                                        hot_rows=ch["hot_rows"], ws=ws_ch, out=(out_s, out_c)),
+                         max(K // 2, 10), 1, stream)
+            rc = out_s.cpu().numpy().copy()
+            del ws_ch
             sweep_s.append({"zipf_s": s, "identity_tuples_per_s": F / (ms_i * 1e-3),
                             "skew_tuples_per_s": F / (ms_s * 1e-3), "speedup": ms_i / ms_s,
-                            "layouts_agree": bool((ri == rs).all())})
+                            "model_choice": {"hot_rows": ch["hot_rows"], "partitioned": ch["partitioned"],
+                                             "l2_hit": round(ch["l2_hit"], 4), "cold_share": round(ch["cold_share"], 4),
+                                             "tuples_per_s": F / (ms_c * 1e-3)},
+                            "layouts_agree": bool((ri == rs).all() and (ri == rc).all())})
             del d, L
             torch.cuda.empty_cache()
         result["zipf_sweep"] = sweep_s
@@ -439,6 +460,16 @@ def bench_group_by(K, WU, dev, stream):
             dg = hashlib.sha256(out[0].cpu().numpy().tobytes() + out[1].cpu().numpy().tobytes()).hexdigest()[:16]
             sweep.append({"form": form, "hot_groups": t, "ms": round(ms, 4), "tuples_per_s": F / (ms * 1e-3),
                           "same_result": dg == res["skew"]["sum_digest"]})
+    # the library's threshold prior for the group-by
+    ch = skew.group_choose(L.counts_by_rank, F)
+    ws_ch = gws if ch["partitioned"] else gws1
+    t_ch = ch["hot_rows"] if ch["hot_rows"] > 0 else (0 if ch["partitioned"] else skew.SKEW_HOT_NONE)
+    ms_ch = timed(lambda: skew.group_aggregate(L.fact_recoded, V, M, hot_groups=t_ch, perm=L.perm, ws=ws_ch, out=out),
+                  max(K // 2, 10), 1, stream)
+    dg = hashlib.sha256(out[0].cpu().numpy().tobytes() + out[1].cpu().numpy().tobytes()).hexdigest()[:16]
+    best = min(sweep, key=lambda r: r["ms"])
+    model_choice = dict(ch, ms=round(ms_ch, 4), same_result=dg == res["skew"]["sum_digest"],
+                        sweep_best={"form": best["form"], "hot_groups": best["hot_groups"], "ms": best["ms"]})
     skew.profile_report()
     skew.profile_enable(True)
     for _ in range(3):
@@ -452,7 +483,7 @@ def bench_group_by(K, WU, dev, stream):
             "runs": res, "speedup_vs_identity": res["identity"]["ms"] / ms,
             "speedup_vs_best_identity": min(r["ms"] for n, r in res.items() if n.startswith("identity")) / ms,
             "roofline_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "stages_ms": stages,
-            "hot_group_sweep": sweep,
+            "hot_group_sweep": sweep, "model_choice": model_choice,
             "build_s_incl_sync": build_s,
             "layouts_agree": len({r["sum_digest"] for r in res.values()}) == 1}
 
@@ -535,7 +566,8 @@ def bench_star(K, dev, stream):
 def bench_serve(seconds, dev):
     """Serving loop: Poisson arrivals at 200 requests/s of grouped aggregations over row ranges (log-uniform
     1e5..5e8 rows) of the resident group-by table (5e8 rows, 1e6 groups, Zipf 1.1); slots from a 16 GB memory
-    budget; at 30 s a new table version with re-permuted popularity arrives (drift, rebuild)."""
+    budget; at 15 s 1e7 rows are inserted (recoded through the current layout, no rebuild); at 30 s a new table
+    version with re-permuted popularity arrives (drift, rebuild)."""
     import torch
 
     from paper_1910_10063_amd import serving
@@ -554,9 +586,16 @@ def bench_serve(seconds, dev):
     t0 = time.time()
     serving.start_layout(srv, tabs[0])
     first_build_s = time.time() - t0
+    # at 15 s, 1e7 rows (keys resampled from the table) are inserted and served on the current layout without a
+    # rebuild (Section 3.1's maintenance); at 30 s a version with re-permuted popularity arrives (drift, rebuild)
+    n_ins = 10_000_000
+    g = torch.Generator(device=dev).manual_seed(19)
+    pick = torch.randint(0, F, (n_ins,), device=dev, generator=g)
+    ins = serving.InsertBatch(tabs[0].keys[pick].contiguous(), tabs[0].vals[pick].contiguous())
     arr = serving.poisson_arrivals(200.0, float(seconds), 17)
-    reqs = serving.make_requests(arr, F, 100_000, F, 17)
-    versions = [(30.0, tabs[1])] if seconds > 30 else []
+    reqs = serving.make_requests(arr, F + n_ins, 100_000, F, 17)
+    versions = [(15.0, ins)] if seconds > 15 else []
+    versions += [(30.0, tabs[1])] if seconds > 30 else []
     done = srv.run(reqs, versions)
     rep = serving.latency_report(done)
     rep.update({"workload": f"grouped aggregation requests over row ranges of a {F:.0e}-row, {M:.0e}-group "
@@ -584,7 +623,7 @@ def bench_cache_model(cbr, rank, N, F, dev):
         out[f"{name}_hit_skew"] = skew.cache_model_hit_rate(cbr, S, 32, ws=ws)
         out[f"{name}_hit_identity"] = skew.cache_model_hit_rate(cbr, S, 32, rank=rank, ws=ws)
     out["seconds_for_4_evaluations"] = round(time.time() - t0, 3)
-    t = min(skew.max_hot_rows(True), N)
+    t = skew.join_hot_rows(F, N, True)
     out["lds_prefix_rows"] = t
     out["lds_prefix_share"] = float(cbr[:t].to(torch.int64).sum().item()) / F
     return out

@@ -106,6 +106,34 @@ int build_skew_layout(const int32_t *fact_keys, int64_t n_fact, int32_t n_keys, 
                       size_t workspace_bytes, void *stream);
 
 /*
+ * append_skew_layout - maintenance of a layout without a rebuild (Section
+ * 3.1): dimension rows inserted after the build are appended to the
+ * dimension and to the end of the permutation index as its least frequent
+ * items, and fact rows inserted afterwards are recoded through the extended
+ * index; their frequencies are not counted (the layout drifts from the true
+ * order until it is rebuilt, and stays exact).
+ *
+ *   n_old, n_new           dimension rows before and after (1 <= n_old <= n_new).
+ *   perm[n_new], rank[n_new]
+ *                          in: the layout of the first n_old rows; out: rows
+ *                          [n_old, n_new) get perm[i] = rank[i] = i.
+ *   counts_by_rank[n_new]  nullable: 0 for the new ranks.
+ *   dim_price[n_new], dim_category[n_new]
+ *                          the dimension in its original order, new rows at the
+ *                          end (each nullable, with its output).
+ *   price_out[n_new], category_out[n_new]
+ *                          the permuted copy; rows [n_old, n_new) are appended.
+ *   fact_keys_new[n_fact_new]     new fact keys in [0, n_new) (original ids).
+ *   fact_recoded_new[n_fact_new]  out: rank[fact_keys_new[j]] (may alias); a key
+ *                          outside [0, n_new) is copied unchanged, and the
+ *                          queries flag it.
+ * Stream-ordered, no wait.  Needs no workspace.
+ */
+int append_skew_layout(int32_t n_old, int32_t n_new, int32_t *perm, int32_t *rank, uint32_t *counts_by_rank,
+                       const int32_t *dim_price, const int8_t *dim_category, int32_t *price_out, int8_t *category_out,
+                       const int32_t *fact_keys_new, int64_t n_fact_new, int32_t *fact_recoded_new, void *stream);
+
+/*
  * fk_join_aggregate - foreign-key join of a fact column with a dimension table,
  * filtered and aggregated (Q1/Q2 of Section 1 feeding SUM and COUNT), with
  * threshold-based processing of the hot prefix (Section 4.2).
@@ -332,16 +360,49 @@ int star_join_batch(const int32_t *prod_keys, const int32_t *cust_keys, const in
 
 /*
  * star_join_autotune - the autotuner of star_join_batch: runs the batch with
- * each candidate split of LDS between the two hot prefixes and each tile size,
- * timing every run with HIP events on `stream`, and writes the fastest tuning
- * to *best and its time (ms) to *best_ms.  Same arguments as star_join_batch
- * (the outputs hold the last run's result).  Waits for the stream.
+ * each candidate split of LDS between the two hot prefixes, each tile size and
+ * each persistent-workgroup count (one and two per compute unit), one warm-up
+ * and three runs each timed with HIP events on `stream`, and writes the tuning
+ * of the smallest median to *best and that median (ms) to *best_ms.  Same
+ * arguments as star_join_batch (the outputs hold the last run's result).
+ * Waits for the stream.
  */
 int star_join_autotune(const int32_t *prod_keys, const int32_t *cust_keys, const int64_t *query_start,
                        const int32_t *query_cust_lt, int32_t n_queries, const int32_t *prod_price,
                        const int8_t *prod_category, int32_t n_prod, const int8_t *cust_segment, int32_t n_cust,
                        int64_t *out_sum, int64_t *out_count, skew_star_tuning *best, float *best_ms,
                        void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Threshold prior of the queries (Section 4.2: the hot rows are those the
+ * cache holds; Section 3.3: the stack-distance model of the other lookups).
+ * skew_join_choose and skew_group_choose read the frequencies of a layout
+ * (counts_by_rank of build_skew_layout, device) and pick:
+ *   hot_rows     the leading ranks, within the LDS capacity, whose keys would
+ *                move more bytes through the cold path than copying the row
+ *                into every workgroup costs;
+ *   partitioned  1 when the partitioned form is modelled to move fewer HBM
+ *                bytes than the single pass: pass a SKEW_OP_JOIN / SKEW_OP_GROUP
+ *                workspace; 0: a *_SINGLE_PASS workspace.
+ * and report the modelled quantities.  l2_hit is the model's LRU hit rate of
+ * the lookups at or above hot_rows in one XCD's 4 MB L2 (32768 lines of 128
+ * bytes; frequency-ordered lines of 32 dimension words, or of 16 groups'
+ * 8-byte accumulators).  workspace >= skew_workspace_bytes(SKEW_OP_CACHE_MODEL,
+ * 0, n_keys).  The calls wait for the stream.  The answer of the query never
+ * depends on the choice.
+ */
+typedef struct {
+  int32_t hot_rows;
+  int32_t partitioned;
+  double cold_share;        /* fact rows at or above hot_rows / n_fact */
+  double l2_hit;            /* modelled L2 hit rate of those rows' lookups */
+  double bytes_single;      /* modelled HBM bytes of the single pass */
+  double bytes_partitioned; /* modelled HBM bytes of the partitioned form */
+} skew_choice;
+int skew_join_choose(const uint32_t *counts_by_rank, int32_t n_keys, int64_t n_fact, int32_t group_by_category,
+                     skew_choice *out, void *workspace, size_t workspace_bytes, void *stream);
+int skew_group_choose(const uint32_t *counts_by_rank, int32_t n_groups, int64_t n_fact, skew_choice *out,
+                      void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * skew_query_status - wait for `stream`, then report whether the last query
@@ -381,6 +442,12 @@ int skew_profile_report(char *names, int names_bytes, float *ms, int *calls, int
  * of the partitioned group-by (8 bytes per group; it may hold a few more when
  * there are fewer slices); the single pass holds fewer (12 bytes per group). */
 int32_t skew_max_hot_rows(int32_t group_by_category);
+/* The hot prefix fk_join_aggregate uses for these arguments (hot_rows as the
+ * call takes it, workspace_bytes as passed to it).  Its partitioned form
+ * shares LDS between the prefix and the buckets of cold keys, so it may use
+ * less than skew_max_hot_rows; a negative code on bad arguments. */
+int32_t skew_join_hot_rows(int64_t n_fact, int32_t n_rows, int32_t group_by_category, int32_t hot_rows,
+                           size_t workspace_bytes);
 int32_t skew_max_hot_groups(void);
 /* op: SKEW_OP_MATERIALIZE (rows), SKEW_OP_SELECT (rows, i.e. bits), SKEW_OP_HEAVY
  * (ranks counted in LDS; ranks in [capacity, k) use global atomics),

@@ -55,6 +55,8 @@ def bind(path: str):
     lib.oracle_group_aggregate.restype = I64
     lib.oracle_build_layout.argtypes = [P, I64, I32, P, P, P, P, P, P, P, P]
     lib.oracle_build_layout.restype = I64
+    lib.oracle_append_layout.argtypes = [I32, I32, P, P, P, P, P, P, P, I64, P]
+    lib.oracle_append_layout.restype = I64
     lib.oracle_materialize.argtypes = [P, I64, P, I32, P]
     lib.oracle_materialize.restype = I64
     lib.oracle_select.argtypes = [P, I64, P, I32, I32, P]
@@ -238,3 +240,29 @@ def build_layout(C, n_keys: int, price=None, category=None) -> Layout:
     inv = _load().oracle_build_layout(_p(C), C.size, n_keys, _p(price), _p(category), _p(perm), _p(rank),
                                       _p(cbr), _p(Cn), _p(pn), _p(cn))
     return Layout(perm, rank, cbr, Cn, pn, cn, int(inv))
+
+
+def append_layout(layout: Layout, n_new: int, price=None, category=None, C_add=None):
+    """Index maintenance without a rebuild (Section 3.1): the layout of n_old = layout.perm.size dimension rows
+    extended to n_new rows (new ids become the least frequent items) and the fact rows C_add recoded through it.
+    price/category are the whole new dimension columns (n_new rows).  Returns (perm, rank, price', category',
+    C_add', invalid)."""
+    n_old = layout.perm.size
+    perm = np.empty(n_new, dtype=np.int32)
+    rank = np.empty(n_new, dtype=np.int32)
+    perm[:n_old] = layout.perm
+    rank[:n_old] = layout.rank
+    pn = cn = None
+    if price is not None:
+        price = _c(price, np.int32)
+        pn = np.empty(n_new, dtype=np.int32)
+        pn[:n_old] = layout.price
+    if category is not None:
+        category = _c(category, np.int8)
+        cn = np.empty(n_new, dtype=np.int8)
+        cn[:n_old] = layout.category
+    C_add = _c(C_add if C_add is not None else np.zeros(0, np.int32), np.int32)
+    out = np.empty_like(C_add)
+    inv = _load().oracle_append_layout(n_old, n_new, _p(perm), _p(rank), _p(price), _p(category), _p(pn), _p(cn),
+                                       _p(C_add), C_add.size, _p(out))
+    return perm, rank, pn, cn, out, int(inv)

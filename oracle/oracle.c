@@ -175,6 +175,32 @@ int64_t oracle_build_layout(const int32_t *C, int64_t n_fact, int32_t n_keys, co
 }
 
 /*
+ * Maintenance of the permutation index without a rebuild (Section 3.1): a
+ * dimension row inserted at the end of the dimension (ids n_old..n_new-1)
+ * joins the end of the permutation index as the new least frequent item, so
+ * Perm(i) = Rank(i) = i for it and its columns land at the end of the
+ * permuted copy; fact rows inserted afterwards are recoded through the
+ * extended rank form, their frequencies ignored.  perm/rank/price_new/
+ * category_new hold the layout of the first n_old rows and have room for
+ * n_new.  Returns the number of new fact keys outside [0, n_new) (copied
+ * unchanged by the recode).
+ */
+int64_t oracle_append_layout(int32_t n_old, int32_t n_new, int32_t *perm, int32_t *rank, const int32_t *price,
+                             const int8_t *category, int32_t *price_new, int8_t *category_new, const int32_t *C_add,
+                             int64_t n_add, int32_t *C_add_new) {
+  for (int32_t i = n_old; i < n_new; ++i) {
+    perm[i] = i;
+    rank[i] = i;
+    if (price && price_new) price_new[i] = price[i];
+    if (category && category_new) category_new[i] = category[i];
+  }
+  int64_t invalid = 0;
+  for (int64_t j = 0; j < n_add; ++j) invalid += (C_add[j] < 0 || C_add[j] >= n_new);
+  oracle_recode(C_add, n_add, rank, n_new, C_add_new);
+  return invalid;
+}
+
+/*
  * Materialization (Q1 of Section 1, operator of Section 4.1): the dimension
  * column gathered through the foreign key, out[j] = col[C[j]].  A key outside
  * [0, n_rows) materializes 0; the number of such keys is returned.

@@ -45,6 +45,9 @@ __global__ void join_pack_kernel(const int32_t *__restrict__ price, const int8_t
 
 constexpr int kJoinVecs = 4;  // 16-byte key vectors per lane per batch
 constexpr int64_t kJoinAutoMinHot = 8192;  // smallest automatic prefix of the single pass
+// Pass 1 counts the keys of slice 0 once per slot below this prefix: on a frequency-ordered layout slice 0
+// then holds more than a sixth of the cold keys (at Zipf 1), and one counter would take many lanes per slot.
+constexpr int32_t kCombineBelow = 16384;
 
 // Accumulators.  GROUPS == 16: every lane owns one 64-bit bin per group in
 // LDS, shared by the 16 waves of the workgroup through LDS atomics (two lanes
@@ -53,7 +56,7 @@ constexpr int64_t kJoinAutoMinHot = 8192;  // smallest automatic prefix of the s
 // GROUPS == 1: sums in registers.
 template <int GROUPS>
 struct JoinCtx {
-  uint64_t *bins;  // LDS [kJoinBins][64]
+  uint64_t *bins;  // LDS [kJoinBinRows][64]
   uint64_t sum;
   uint32_t cnt;
   bool bad;
@@ -80,7 +83,7 @@ __device__ __forceinline__ void join_init(JoinCtx<GROUPS> &c, unsigned char *sme
   c.out_sum = out_sum;
   c.out_cnt = out_cnt;
   if (GROUPS == 16)
-    for (int i = threadIdx.x; i < kJoinBins * kWave; i += blockDim.x) c.bins[i] = 0;
+    for (int i = threadIdx.x; i < kJoinBinRows * kWave; i += blockDim.x) c.bins[i] = 0;
 }
 
 template <int GROUPS>
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(kJoinThreads) void join_kernel(const int32_t *__res
                                                             int64_t *__restrict__ out_sum,
                                                             int64_t *__restrict__ out_cnt, int32_t *flag) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int kBinBytes = GROUPS == 16 ? kJoinBins * kWave * 8 : 0;
+  constexpr int kBinBytes = GROUPS == 16 ? kJoinBinRows * kWave * 8 : 0;
   JoinCtx<GROUPS> c;
   join_init(c, smem, price, cat, cat_lt, n_rows, out_sum, out_cnt);
   uint32_t *hot = reinterpret_cast<uint32_t *>(smem + kBinBytes);
@@ -299,7 +302,8 @@ __device__ __forceinline__ void join_split_batch(JoinCtx<GROUPS> &c, const ColdS
     join_add(c, w[i]);
   }
   if (__builtin_expect(!(all & kValid), 0)) join_slow_batch(c, w, k);  // a hot row whose price escapes
-  cold_append(o, k, cold, [&](int i, int32_t idx) { buffer_store_record((int32_t)k[i], seg, idx, 0, 0, 0); });
+  auto st = [&](int i, int32_t idx) { buffer_store_record((int32_t)k[i], seg, idx, 0, 0, 0); };
+  cold_append<4 * V, decltype(st), true>(o, k, cold, st);
 }
 
 template <int GROUPS>
@@ -325,7 +329,7 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
     int64_t *__restrict__ out_sum, int64_t *__restrict__ out_cnt, int32_t *flag, int32_t *__restrict__ cold_seg,
     int64_t seg_cap, uint32_t *__restrict__ seg_count, uint32_t *__restrict__ hist) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int kBinBytes = GROUPS == 16 ? kJoinBins * kWave * 8 : 0;
+  constexpr int kBinBytes = GROUPS == 16 ? kJoinBinRows * kWave * 8 : 0;
   JoinCtx<GROUPS> c;
   join_init(c, smem, price, cat, cat_lt, n_rows, out_sum, out_cnt);
   uint32_t *hot = reinterpret_cast<uint32_t *>(smem + kBinBytes);
@@ -345,6 +349,7 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
   o.t = (uint32_t)t_lds;
   o.wshift = wshift;
   o.sink = (uint32_t)P + lane_id();
+  o.combine0 = t_lds < kCombineBelow;  // below it slice 0 takes a large share of the cold keys
   const uint32_t tclamp = t_lds > 0 ? (uint32_t)t_lds - 1 : 0u;
   const Tail tail{(uint32_t)tail_start, record_buffer(words, (uint32_t)n_rows)};
 
@@ -476,7 +481,7 @@ __global__ __launch_bounds__(kJoinThreads) void join_slice_kernel(
     const int8_t *__restrict__ cat, int32_t cat_lt, int64_t *__restrict__ out_sum, int64_t *__restrict__ out_cnt,
     int32_t *flag) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int kBinBytes = GROUPS == 16 ? kJoinBins * kWave * 8 : 0;
+  constexpr int kBinBytes = GROUPS == 16 ? kJoinBinRows * kWave * 8 : 0;
   JoinCtx<GROUPS> c;
   join_init(c, smem, price, cat, cat_lt, n_rows, out_sum, out_cnt);
   const int32_t W = 1 << wshift;
@@ -529,7 +534,7 @@ void allow_lds(K kernel, size_t bytes) {
 // ---------------------------------------------------------------------------
 size_t join_lds_bytes(int groups, int32_t hot_rows) {
   const size_t hot = (((size_t)(hot_rows > 0 ? hot_rows : 0) + 4) & ~(size_t)3) * 4;
-  return (groups == 16 ? (size_t)kJoinBins * kWave * 8 : 0) + hot;
+  return (groups == 16 ? (size_t)kJoinBinRows * kWave * 8 : 0) + hot;
 }
 
 int32_t join_max_hot_rows(int groups, const DeviceInfo &dev) {
@@ -565,6 +570,30 @@ size_t join_partition_bytes(const JoinPlan &pl) {
          + r((size_t)P * 4) + r(4) + r((size_t)pl.blocks * 4) + r((size_t)(P + 1) * 4);
 }
 
+int32_t join_hot_rows_used(int64_t n_fact, int32_t n_rows, int32_t by_cat, int32_t hot_rows, size_t part_bytes,
+                           const DeviceInfo &dev, bool *partitioned) {
+  const int groups = by_cat ? 16 : 1;
+  int32_t t = hot_rows;
+  const int32_t cap = join_max_hot_rows(groups, dev);
+  if (t < 0 || t > cap) t = cap;
+  if (t > n_rows) t = n_rows;
+  const JoinPlan pl = join_plan(n_fact, n_rows, t, groups, dev);
+  *partitioned = part_bytes > 0 && n_fact >= kPartitionMinFact && pl.slices > 0 &&
+                 part_bytes >= join_partition_bytes(pl);
+  if (!*partitioned && hot_rows < 0) {
+    // Every workgroup of the single pass copies the prefix into LDS: for a small input, a prefix much longer
+    // than half the keys a workgroup reads costs more to stage than its lookups save (8192 rows at 1e6-4e6
+    // keys).
+    const int64_t per_launch_max = (int64_t)dev.cu_count * kJoinThreads * (1LL << 14);
+    const int64_t n0 = n_fact < per_launch_max ? n_fact : per_launch_max;
+    const int64_t need = (n0 + 4LL * kJoinThreads - 1) / (4LL * kJoinThreads);
+    const int64_t per_wg = n0 / (need < dev.cu_count ? need : dev.cu_count);
+    const int64_t ta = per_wg / 2 > kJoinAutoMinHot ? per_wg / 2 : kJoinAutoMinHot;
+    if (ta < t) t = (int32_t)ta;
+  }
+  return t;
+}
+
 hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price, const int8_t *cat, int32_t n_rows,
                        int32_t cat_lt, int32_t by_cat, int32_t hot_rows, int64_t *out_sum, int64_t *out_cnt,
                        uint32_t *words, int32_t *flag, void *part_ws, size_t part_bytes, const DeviceInfo &dev,
@@ -576,29 +605,14 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
   hipError_t e = hipGetLastError();
   stage_end(st, s);
   if (e != hipSuccess || n_fact == 0) return e;
-  const bool auto_t = hot_rows < 0;  // SKEW_HOT_AUTO
-  int32_t t = hot_rows;
-  const int32_t cap = join_max_hot_rows(groups, dev);
-  if (auto_t || t > cap) t = cap;
-  if (t > n_rows) t = n_rows;
-
+  bool partitioned = false;
+  const int32_t t = join_hot_rows_used(n_fact, n_rows, by_cat, hot_rows, part_ws ? part_bytes : 0, dev, &partitioned);
   const JoinPlan pl = join_plan(n_fact, n_rows, t, groups, dev);
-  const bool partitioned = part_ws && n_fact >= kPartitionMinFact && pl.slices > 0 &&
-                           part_bytes >= join_partition_bytes(pl);
   if (!partitioned) {
     const size_t lds = join_lds_bytes(groups, t);
     // Every lane's bins must see fewer than 2^19 rows per launch: at most 16
     // waves share a bin, so a thread handles at most 2^14 rows per launch.
     const int64_t per_launch_max = (int64_t)dev.cu_count * kJoinThreads * (1LL << 14);
-    if (auto_t) {
-      // Every workgroup copies the prefix into LDS: for a small input, a prefix much longer than half the
-      // keys a workgroup reads costs more to stage than its lookups save (8192 rows at 1e6-4e6 keys).
-      const int64_t n0 = n_fact < per_launch_max ? n_fact : per_launch_max;
-      const int64_t need = (n0 + 4LL * kJoinThreads - 1) / (4LL * kJoinThreads);
-      const int64_t per_wg = n0 / (need < dev.cu_count ? need : dev.cu_count);
-      const int64_t ta = per_wg / 2 > kJoinAutoMinHot ? per_wg / 2 : kJoinAutoMinHot;
-      if (ta < t) t = (int32_t)ta;
-    }
     if (groups == 16) allow_lds(join_kernel<16>, lds);
     else allow_lds(join_kernel<1>, lds);
     for (int64_t off = 0; off < n_fact; off += per_launch_max) {
@@ -638,7 +652,7 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
   tab.slice_off = (uint32_t *)ws;
 
   const size_t lds1 = join_lds_bytes(groups, t) + (size_t)(pl.slices + kWave + 4) * 4;
-  const size_t lds3 = (groups == 16 ? (size_t)kJoinBins * kWave * 8 : 0) + ((size_t)4 << pl.wshift) +
+  const size_t lds3 = (groups == 16 ? (size_t)kJoinBinRows * kWave * 8 : 0) + ((size_t)4 << pl.wshift) +
                       (size_t)(pl.slices + 1) * 4;
   // keys past the last slice (dimensions of more than kMaxSlices slices) are gathered in pass 1
   const int64_t tail_row = (int64_t)t + ((int64_t)pl.slices << pl.wshift);

@@ -30,6 +30,10 @@ hipError_t launch_permute_dims(const int32_t *perm, int32_t n, const int32_t *pr
                                int32_t *price_out, int8_t *cat_out, hipStream_t s);
 hipError_t launch_recode(const int32_t *keys, int64_t n, const int32_t *rank, const int32_t *perm, int32_t n_keys,
                          int32_t *out, const DeviceInfo &dev, hipStream_t s);
+// Dimension rows [from, to) appended to a layout as its least frequent items.
+hipError_t launch_append_rows(int32_t from, int32_t to, int32_t *perm, int32_t *rank, uint32_t *counts_by_rank,
+                              const int32_t *price, const int8_t *cat, int32_t *price_out, int8_t *cat_out,
+                              hipStream_t s);
 
 // ---- prefix sums and cold-item partitioning ----
 struct SliceTables;
@@ -84,6 +88,10 @@ size_t join_lds_bytes(int groups, int32_t hot_rows);
 int32_t join_max_hot_rows(int groups, const DeviceInfo &dev);
 JoinPlan join_plan(int64_t n_fact, int32_t n_rows, int32_t t, int groups, const DeviceInfo &dev);
 size_t join_partition_bytes(const JoinPlan &pl);
+// Prefix the join uses for these sizes and partition workspace; *partitioned
+// tells which form runs.
+int32_t join_hot_rows_used(int64_t n_fact, int32_t n_rows, int32_t by_cat, int32_t hot_rows, size_t part_bytes,
+                           const DeviceInfo &dev, bool *partitioned);
 size_t group_lds_bytes(int32_t hot_groups);
 int32_t group_max_hot_groups(const DeviceInfo &dev);  // single pass
 size_t group_split_lds_bytes(int32_t hot_groups, int32_t slices);

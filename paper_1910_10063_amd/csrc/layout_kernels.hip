@@ -15,6 +15,23 @@ __global__ void fill_u32_kernel(uint32_t *__restrict__ p, int64_t n, uint32_t v)
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
+// Index maintenance (Section 3.1): dimension rows [from, to) appended after
+// the build become the least frequent items, Perm(i) = Rank(i) = i, with no
+// occurrences counted; their columns go to the end of the permuted copy.
+__global__ void append_rows_kernel(int32_t from, int32_t to, int32_t *__restrict__ perm, int32_t *__restrict__ rank,
+                                   uint32_t *__restrict__ counts_by_rank, const int32_t *__restrict__ price,
+                                   const int8_t *__restrict__ cat, int32_t *__restrict__ price_out,
+                                   int8_t *__restrict__ cat_out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < to; i += stride) {
+    perm[i] = (int32_t)i;
+    rank[i] = (int32_t)i;
+    if (counts_by_rank) counts_by_rank[i] = 0;
+    if (price) price_out[i] = price[i];
+    if (cat) cat_out[i] = cat[i];
+  }
+}
+
 int grid_1d(int64_t n, int threads, int cap) {
   int64_t g = (n + threads - 1) / threads;
   if (g > cap) g = cap;
@@ -468,6 +485,15 @@ hipError_t launch_rank_sort(const uint32_t *counts_by_key, int32_t n_keys, int64
 hipError_t launch_inverse(const int32_t *perm, int32_t n, int32_t *rank, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(inverse_kernel, dim3(grid_1d(n, 256, 16384)), dim3(256), 0, s, perm, n, rank);
+  return hipGetLastError();
+}
+
+hipError_t launch_append_rows(int32_t from, int32_t to, int32_t *perm, int32_t *rank, uint32_t *counts_by_rank,
+                              const int32_t *price, const int8_t *cat, int32_t *price_out, int8_t *cat_out,
+                              hipStream_t s) {
+  if (to <= from) return hipSuccess;
+  hipLaunchKernelGGL(append_rows_kernel, dim3(grid_1d(to - from, 256, 16384)), dim3(256), 0, s, from, to, perm, rank,
+                     counts_by_rank, price, cat, price_out, cat_out);
   return hipGetLastError();
 }
 

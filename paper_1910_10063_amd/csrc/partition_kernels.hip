@@ -171,6 +171,10 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
   const int b = blockIdx.x, B = gridDim.x, tid = threadIdx.x;
   for (int p = tid; p < P; p += blockDim.x) run[p] = slice_off[p] + hist[(int64_t)p * B + b];
   const uint32_t cnt = seg_count[b];
+  // this block's items of slice 0 (the row scan left exclusive prefixes over the blocks): when they are a
+  // quarter of its segment or more, the lanes of a load that fall into slice 0 take their ranks together
+  const uint32_t n0 = (b + 1 < B ? hist[b + 1] : slice_off[1] - slice_off[0]) - hist[b];
+  const bool combine0 = 4ull * n0 >= (uint64_t)cnt && cnt > 0;
   // segments start 16-byte aligned and hold a multiple of 4 slots, so every
   // vector that starts below cnt lies inside the segment
   const i32x4 *sk = reinterpret_cast<const i32x4 *>(seg_keys + (int64_t)b * seg_cap);
@@ -205,7 +209,19 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const uint32_t i = 4 * ((uint32_t)u * kScatterThreads + tid) + j;  // item within the tile
-        rk[4 * u + j] = i < n ? atomicAdd(&start[slice_of(kv[j])], 1u) : 0u;  // rank among the tile's items of the slice
+        // rank among the tile's items of the slice; the lanes whose items fall into slice 0 (the densest
+        // one on a frequency-ordered layout) take consecutive ranks with one LDS add
+        const uint32_t sl = slice_of(kv[j]);
+        if (combine0) {
+          const bool z = i < n && sl == 0;
+          const uint64_t mz = __ballot(z);
+          uint32_t base0 = 0;
+          if (z && lanes_below(mz) == 0) base0 = atomicAdd(&start[0], (uint32_t)__popcll(mz));
+          base0 = (uint32_t)__shfl((int)base0, (int)(__ffsll((unsigned long long)mz) - 1) & (kWave - 1), kWave);
+          rk[4 * u + j] = z ? base0 + lanes_below(mz) : (i < n ? atomicAdd(&start[sl], 1u) : 0u);
+        } else {
+          rk[4 * u + j] = i < n ? atomicAdd(&start[sl], 1u) : 0u;
+        }
       }
     }
     if (base + kScatterTile < cnt) load_tile(kn, vn, base + kScatterTile);

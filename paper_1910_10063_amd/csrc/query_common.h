@@ -23,6 +23,7 @@ constexpr uint32_t kValid = 0x80000000u;
 constexpr int kGroupShift = 25;
 constexpr uint32_t kPriceMask = (1u << kGroupShift) - 1u;
 constexpr int kJoinBins = 32;  // (w >> 25) & 31
+constexpr int kJoinBinRows = 17;  // bins a word can select: 0 (sink) and 1..16 (groups)
 constexpr int kCountShift = 44;  // a join bin packs count << 44 | sum
 constexpr uint64_t kSumMask = (1ull << kCountShift) - 1ull;
 
@@ -92,6 +93,7 @@ struct ColdSink {
   uint32_t t;
   int32_t wshift;
   uint32_t sink;    // P + lane
+  bool combine0 = false;  // count slice 0 with one add per slot (cold_append<..., true>)
 };
 
 // Number of lanes below this one in mask m.
@@ -109,7 +111,10 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t *count, uint32_t n) {
 }
 
 // store(i, idx) writes slot i at segment index idx (idx = -1: out of range).
-template <int N, class Store>
+// With COMBINE0 and o.combine0, the lanes of a slot whose keys fall into
+// slice 0 (the densest one on a frequency-ordered layout) are counted by one
+// LDS add instead of one each, so they do not queue on the same counter.
+template <int N, class Store, bool COMBINE0 = false>
 __device__ __forceinline__ void cold_append(const ColdSink &o, const uint32_t (&k)[N], const bool (&cold)[N],
                                             Store store) {
   constexpr int kPart = N < 8 ? N : 8;  // ballots live at once
@@ -128,7 +133,15 @@ __device__ __forceinline__ void cold_append(const ColdSink &o, const uint32_t (&
     for (int i = 0; i < kPart; ++i) {
       const bool cd = cold[p0 + i];
       store(p0 + i, cd ? (int32_t)(pos + lanes_below(m[i])) : -1);
-      lds_add_u32(&o.hist[cd ? (k[p0 + i] - o.t) >> o.wshift : o.sink], 1u);
+      const uint32_t sl = (k[p0 + i] - o.t) >> o.wshift;
+      bool one = cd;
+      if (COMBINE0 && o.combine0) {
+        const bool z = cd && sl == 0;
+        const uint64_t mz = __ballot(z);
+        if (z && lanes_below(mz) == 0) lds_add_u32(&o.hist[0], (uint32_t)__popcll(mz));
+        one = cd && !z;
+      }
+      lds_add_u32(&o.hist[one ? sl : o.sink], 1u);
       pos += (uint32_t)__popcll(m[i]);
     }
   }

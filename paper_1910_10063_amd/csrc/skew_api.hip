@@ -3,6 +3,7 @@
 // caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -344,6 +345,32 @@ int join_check(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_pric
 
 }  // namespace
 
+int append_skew_layout(int32_t n_old, int32_t n_new, int32_t *perm, int32_t *rank, uint32_t *counts_by_rank,
+                       const int32_t *dim_price, const int8_t *dim_category, int32_t *price_out, int8_t *category_out,
+                       const int32_t *fact_keys_new, int64_t n_fact_new, int32_t *fact_recoded_new, void *stream) {
+  if (n_old < 1 || n_new < n_old) return fail(SKEW_EINVAL, "need 1 <= n_old <= n_new");
+  if (n_fact_new < 0) return fail(SKEW_EINVAL, "n_fact_new must be >= 0");
+  if (!perm || !rank) return fail(SKEW_EINVAL, "perm and rank are required");
+  if ((dim_price == nullptr) != (price_out == nullptr))
+    return fail(SKEW_EINVAL, "dim_price and price_out must both be set or both be NULL");
+  if ((dim_category == nullptr) != (category_out == nullptr))
+    return fail(SKEW_EINVAL, "dim_category and category_out must both be set or both be NULL");
+  if (n_fact_new > 0 && (!fact_keys_new || !fact_recoded_new))
+    return fail(SKEW_EINVAL, "fact_keys_new and fact_recoded_new are required");
+  if (!aligned4(perm) || !aligned4(rank) || !aligned4(counts_by_rank) || !aligned4(dim_price) || !aligned4(price_out) ||
+      !aligned4(fact_keys_new) || !aligned4(fact_recoded_new))
+    return fail(SKEW_EINVAL, "32-bit arrays must be 4-byte aligned");
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const hipStream_t s = (hipStream_t)stream;
+  hipError_t e = skew::launch_append_rows(n_old, n_new, perm, rank, counts_by_rank, dim_price, dim_category,
+                                          price_out, category_out, s);
+  if (e == hipSuccess)
+    e = skew::launch_recode(fact_keys_new, n_fact_new, rank, perm, n_new, fact_recoded_new, dev, s);
+  if (e != hipSuccess) return hip_fail(e, "append launch");
+  return ok();
+}
+
 int fk_join_aggregate(const int32_t *fact_keys, int64_t n_fact, const int32_t *dim_price,
                       const int8_t *dim_category, int32_t n_rows, int32_t cat_lt, int32_t group_by_category,
                       int32_t hot_rows, int64_t *out_sum, int64_t *out_count, void *workspace,
@@ -631,43 +658,184 @@ int star_join_autotune(const int32_t *prod_keys, const int32_t *cust_keys, const
   skew::DeviceInfo dev;
   if (int rc = device_info(&dev)) return rc;
   const hipStream_t s = (hipStream_t)stream;
-  hipEvent_t a = nullptr, b = nullptr;
-  hipError_t e = hipEventCreate(&a);
-  if (e == hipSuccess) e = hipEventCreate(&b);
-  if (e != hipSuccess) return hip_fail(e, "autotune events");
+  constexpr int kReps = 3;  // timed runs per candidate (after one warm-up); the median counts
+  hipEvent_t ev[kReps + 1] = {};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i <= kReps && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  if (e != hipSuccess) {
+    for (hipEvent_t x : ev)
+      if (x) (void)hipEventDestroy(x);
+    return hip_fail(e, "autotune events");
+  }
   const int32_t cust_cand[] = {0, 65536, 262144, 524288, 786432, 1048576};
   const int32_t tile_cand[] = {65536, 262144, 1048576};
+  const int32_t block_cand[] = {dev.cu_count, 2 * dev.cu_count};
   float best_t = -1.f;
   skew_star_tuning arg{-1, 0, 0, 0};
   for (int32_t tc : cust_cand) {
     for (int32_t tr : tile_cand) {
-      arg.cust_hot_rows = tc;
-      arg.tile_rows = tr;
-      const skew_star_tuning t = star_resolve(&arg, n_prod, n_cust, n_queries, dev);
-      float ms = 0.f;
-      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // one warm-up, one timed run
-        if (rep == 1) e = hipEventRecord(a, s);
-        if (e == hipSuccess)
-          e = skew::launch_star(prod_keys, cust_keys, query_start, query_cust_lt, n_queries, prod_price,
-                                prod_category, n_prod, cust_segment, n_cust, t.prod_hot_rows, t.cust_hot_rows,
-                                t.tile_rows, t.blocks, out_sum, out_count, (int32_t *)workspace,
-                                (char *)workspace + skew::kFlagBytes, dev, s);
-        if (rep == 1 && e == hipSuccess) e = hipEventRecord(b, s);
+      for (int32_t nb : block_cand) {
+        arg.cust_hot_rows = tc;
+        arg.tile_rows = tr;
+        arg.blocks = nb;
+        const skew_star_tuning t = star_resolve(&arg, n_prod, n_cust, n_queries, dev);
+        auto run = [&]() {
+          return skew::launch_star(prod_keys, cust_keys, query_start, query_cust_lt, n_queries, prod_price,
+                                   prod_category, n_prod, cust_segment, n_cust, t.prod_hot_rows, t.cust_hot_rows,
+                                   t.tile_rows, t.blocks, out_sum, out_count, (int32_t *)workspace,
+                                   (char *)workspace + skew::kFlagBytes, dev, s);
+        };
+        e = run();  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+        for (int i = 0; i < kReps && e == hipSuccess; ++i) {
+          e = run();
+          if (e == hipSuccess) e = hipEventRecord(ev[i + 1], s);
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[kReps]);
+        float ms[kReps] = {};
+        for (int i = 0; i < kReps && e == hipSuccess; ++i) e = hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]);
+        if (e != hipSuccess) break;
+        std::sort(ms, ms + kReps);
+        const float med = ms[kReps / 2];
+        if (best_t < 0.f || med < best_t) {
+          best_t = med;
+          *best = t;
+        }
       }
-      if (e == hipSuccess) e = hipEventSynchronize(b);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
       if (e != hipSuccess) break;
-      if (best_t < 0.f || ms < best_t) {
-        best_t = ms;
-        *best = t;
-      }
     }
     if (e != hipSuccess) break;
   }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
+  for (hipEvent_t x : ev) (void)hipEventDestroy(x);
   if (e != hipSuccess) return hip_fail(e, "autotune");
   *best_ms = best_t;
+  return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+// Cost model of the threshold choice.  Bytes a fact row at or above t moves in
+// the partitioned forms beyond reading its own columns: the join writes its
+// key to a segment (4), the scatter reads it and writes a 2-byte offset (4 + 2,
+// partial lines widen the writes to about 3), pass 3 reads the offset (2); the
+// group-by moves a 4-byte record four times.
+constexpr double kJoinColdBytes = 13.0;
+constexpr double kGroupColdBytes = 16.0;
+// Fixed cost of one round of a partitioned form (plan kernels and launches,
+// about 20 us), in bytes at the read rate of the device (6 TB/s).
+constexpr double kRoundFixedBytes = 128.0e6;
+constexpr double kLineBytes = 128.0;     // an L2 miss of a gather or an atomic moves one line
+constexpr int64_t kL2Lines = 32768;      // one XCD's 4 MB L2 (each XCD sees the whole access stream)
+
+// counts[0, n) of a device array of frequencies in rank order, added up into
+// prefix[0, n] on the host (waits for the stream).
+int host_prefix(const uint32_t *counts, int32_t n, std::vector<uint64_t> &prefix, hipStream_t s) {
+  std::vector<uint32_t> h((size_t)n);
+  hipError_t e = n > 0 ? hipMemcpyAsync(h.data(), counts, (size_t)n * 4, hipMemcpyDeviceToHost, s) : hipSuccess;
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "copying the frequencies");
+  prefix.assign((size_t)n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) prefix[(size_t)i + 1] = prefix[(size_t)i] + h[(size_t)i];
+  return SKEW_OK;
+}
+
+// Leading ranks (at most cap) whose frequency reaches `threshold` (frequencies
+// do not increase along the ranks).
+int32_t ranks_reaching(const std::vector<uint64_t> &prefix, int32_t cap, double threshold) {
+  int32_t t = 0;
+  while (t < cap && (double)(prefix[(size_t)t + 1] - prefix[(size_t)t]) >= threshold) ++t;
+  return t;
+}
+
+// Modelled L2 hit rate of the lookups of ranks [t, n_keys) (Section 3.3's model, frequency-ordered lines of
+// `per_line` values).
+int residual_hit(const uint32_t *counts, int32_t n_keys, int32_t t, int32_t per_line, double *hit, void *ws,
+                 size_t ws_bytes, const skew::DeviceInfo &dev, hipStream_t s) {
+  *hit = 1.0;
+  if (t >= n_keys) return SKEW_OK;
+  const size_t need = skew::kFlagBytes + round_up(skew::model_workspace_bytes(n_keys - t, per_line));
+  if (ws_bytes < need) return fail(SKEW_ENOSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  const hipError_t e = skew::launch_cache_model(counts + t, n_keys - t, nullptr, per_line, kL2Lines,
+                                                (char *)ws + skew::kFlagBytes, hit, dev, s);
+  return e == hipSuccess ? SKEW_OK : hip_fail(e, "cache model");
+}
+
+}  // namespace
+
+extern "C" {
+
+int skew_join_choose(const uint32_t *counts_by_rank, int32_t n_keys, int64_t n_fact, int32_t group_by_category,
+                     skew_choice *out, void *workspace, size_t workspace_bytes, void *stream) {
+  if (n_keys < 1 || n_fact < 0) return fail(SKEW_EINVAL, "bad sizes");
+  if (!counts_by_rank || !out || !workspace) return fail(SKEW_EINVAL, "counts_by_rank, out and workspace are required");
+  if (group_by_category != 0 && group_by_category != 1) return fail(SKEW_EINVAL, "group_by_category must be 0 or 1");
+  if (!aligned4(counts_by_rank)) return fail(SKEW_EINVAL, "counts_by_rank must be 4-byte aligned");
+  if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const hipStream_t s = (hipStream_t)stream;
+  const int groups = group_by_category ? 16 : 1;
+  const skew::DeviceInfo pdev = part_device(dev);
+  int32_t cap = skew::join_max_hot_rows(groups, dev);
+  if (cap > n_keys) cap = n_keys;
+  std::vector<uint64_t> prefix;
+  if (int rc = host_prefix(counts_by_rank, cap, prefix, s)) return rc;
+  const skew::JoinPlan pl = skew::join_plan(n_fact, n_keys, 0, groups, pdev);
+  const int64_t rounds = pl.round > 0 ? (n_fact + pl.round - 1) / pl.round : 0;
+  // A row earns its place in the LDS prefix when the cold bytes its keys would move exceed the bytes of
+  // copying it into every workgroup of every round.
+  const double stage = 4.0 * pl.blocks * (double)(rounds > 0 ? rounds : 1);
+  const int32_t t = ranks_reaching(prefix, cap, stage / kJoinColdBytes);
+  const double F = (double)n_fact, cold = F - (double)prefix[(size_t)t];
+  double hit = 1.0;
+  if (int rc = residual_hit(counts_by_rank, n_keys, t, 32, &hit, workspace, workspace_bytes, dev, s)) return rc;
+  out->hot_rows = t;
+  out->cold_share = F > 0 ? cold / F : 0.0;
+  out->l2_hit = hit;
+  // The single pass reads the keys and gathers every cold lookup (a line per L2 miss); the partitioned form
+  // moves kJoinColdBytes per cold key and reads every dimension row past t once in pass 3.
+  out->bytes_single = 4.0 * F + cold * (1.0 - hit) * kLineBytes + 4.0 * t * dev.cu_count;
+  out->bytes_partitioned = 4.0 * F + cold * kJoinColdBytes + stage * t + 4.0 * (double)(n_keys - t) +
+                           kRoundFixedBytes * (double)rounds;
+  out->partitioned = n_fact >= skew::kPartitionMinFact && out->bytes_partitioned < out->bytes_single ? 1 : 0;
+  return ok();
+}
+
+int skew_group_choose(const uint32_t *counts_by_rank, int32_t n_groups, int64_t n_fact, skew_choice *out,
+                      void *workspace, size_t workspace_bytes, void *stream) {
+  if (n_groups < 1 || n_fact < 0) return fail(SKEW_EINVAL, "bad sizes");
+  if (!counts_by_rank || !out || !workspace) return fail(SKEW_EINVAL, "counts_by_rank, out and workspace are required");
+  if (!aligned4(counts_by_rank)) return fail(SKEW_EINVAL, "counts_by_rank must be 4-byte aligned");
+  if (!aligned256(workspace)) return fail(SKEW_EINVAL, "workspace must be 256-byte aligned");
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const hipStream_t s = (hipStream_t)stream;
+  const skew::DeviceInfo pdev = part_device(dev);
+  const skew::GroupPlan pl = skew::group_plan(n_fact, n_groups, pdev);
+  const bool can_partition = n_fact >= skew::kPartitionMinFact && pl.slices <= skew::kMaxSlices;
+  int32_t cap = can_partition ? skew::group_split_max_hot_groups(pl.slices, dev) : skew::group_max_hot_groups(dev);
+  if (cap > n_groups) cap = n_groups;
+  std::vector<uint64_t> prefix;
+  if (int rc = host_prefix(counts_by_rank, cap, prefix, s)) return rc;
+  const int64_t rounds = pl.round > 0 ? (n_fact + pl.round - 1) / pl.round : 0;
+  // A group earns its LDS bin when its cold bytes exceed clearing and flushing the bin (a 16-byte sum and
+  // count read, then added to the accumulators by two atomics whose lines stay in L2) in every workgroup of
+  // every round.
+  const double stage = 32.0 * pl.blocks * (double)(rounds > 0 ? rounds : 1);
+  const int32_t t = ranks_reaching(prefix, cap, stage / kGroupColdBytes);
+  const double F = (double)n_fact, cold = F - (double)prefix[(size_t)t];
+  double hit = 1.0;
+  // the cold rows' atomics go to int64 sum and count words: 16 groups per 128-byte line
+  if (int rc = residual_hit(counts_by_rank, n_groups, t, 16, &hit, workspace, workspace_bytes, dev, s)) return rc;
+  out->hot_rows = t;
+  out->cold_share = F > 0 ? cold / F : 0.0;
+  out->l2_hit = hit;
+  out->bytes_single = 8.0 * F + cold * (1.0 - hit) * 2.0 * kLineBytes + stage * t / (double)(rounds > 0 ? rounds : 1);
+  out->bytes_partitioned = 8.0 * F + cold * kGroupColdBytes + stage * t + 16.0 * n_groups +
+                           kRoundFixedBytes * (double)rounds;
+  out->partitioned = can_partition && out->bytes_partitioned < out->bytes_single ? 1 : 0;
   return ok();
 }
 
@@ -724,6 +892,18 @@ int32_t skew_max_hot_rows(int32_t group_by_category) {
   skew::DeviceInfo dev;
   if (int rc = device_info(&dev)) return rc;
   return skew::join_max_hot_rows(group_by_category ? 16 : 1, dev);
+}
+
+int32_t skew_join_hot_rows(int64_t n_fact, int32_t n_rows, int32_t group_by_category, int32_t hot_rows,
+                           size_t workspace_bytes) {
+  if (n_fact < 0 || n_rows < 1 || hot_rows < SKEW_HOT_AUTO || (group_by_category != 0 && group_by_category != 1))
+    return fail(SKEW_EINVAL, "bad sizes or hot_rows");
+  skew::DeviceInfo dev;
+  if (int rc = device_info(&dev)) return rc;
+  const size_t need = join_ws(n_rows);
+  bool partitioned = false;
+  return skew::join_hot_rows_used(n_fact, n_rows, group_by_category, hot_rows,
+                                  workspace_bytes > need ? workspace_bytes - need : 0, part_device(dev), &partitioned);
 }
 
 int32_t skew_max_hot_groups(void) {

@@ -13,6 +13,8 @@ resident fact table (the grouped aggregation Q3 of Section 1).  The server works
   the maintenance discussion there suggests).  A new version of the table, with re-permuted key
   popularity, is served at once on the identity layout with the library's layout-oblivious method, which
   gives the same answers.
+* Rows inserted into the table are recoded through the current layout and served on it at once (the
+  maintenance rule of Section 3.1); their frequencies are not counted.
 * It watches the share of rows that the current layout sends to its hot prefix.  When that share drops
   (drift), it rebuilds the layout on a side stream and switches to the rebuilt layout when it is ready.
 
@@ -58,6 +60,14 @@ class TableVersion:
     n_groups: int
     layout: skew.Layout | None = None
     hot_share: float = math.nan  # share of rows below the hot threshold on its own layout
+
+
+@dataclass
+class InsertBatch:
+    """Fact rows inserted into the current table version (appended at its end)."""
+
+    keys: torch.Tensor  # int32 group ids (identity layout)
+    vals: torch.Tensor  # int32 values
 
 
 @dataclass
@@ -193,6 +203,28 @@ class Server:
             r["thread"].start()
             self.rebuild = r
 
+    def insert(self, batch: InsertBatch) -> TableVersion:
+        """Rows inserted into the table (Section 3.1, maintenance): the next version is the current one with the
+        rows appended.  When the current version is served on its own layout, the new rows are recoded through that
+        layout and the next version is served on it at once, with no rebuild; the new rows' frequencies are not
+        counted, and drift detection decides later whether a rebuild pays."""
+        old = self.current
+        t0 = self.now()
+        tab = TableVersion(old.version + 1, torch.cat([old.keys, batch.keys]), torch.cat([old.vals, batch.vals]),
+                           old.n_groups)
+        if self.serving_layout is old and old.layout is not None:
+            layout, rec = skew.append_skew_layout(old.layout, old.n_groups, fact_keys_new=batch.keys)
+            layout.fact_recoded = torch.cat([old.layout.fact_recoded, rec])
+            tab.layout = layout
+            tab.hot_share = old.hot_share
+            self.serving_layout = tab
+        self.current = tab
+        torch.cuda.current_stream(self.device).synchronize()  # the new version is complete before it is served
+        self.events.append({"t": t0, "event": "insert", "version": tab.version, "rows": batch.keys.numel(),
+                            "served_on": "skew" if tab.layout is not None else "identity",
+                            "ms": (self.now() - t0) * 1e3})
+        return tab
+
     def poll_rebuild(self) -> None:
         r = self.rebuild
         if r is None or r["thread"].is_alive():
@@ -215,6 +247,7 @@ class Server:
         req.version = tab.version
         req.layout = "skew" if use_skew else "identity"
         req.admitted = self.now()
+        req.rows = max(0, min(req.rows, tab.keys.numel() - req.start))
         a, n = req.start, req.rows
         out = req.out if req.out is not None else slot.out
         with torch.cuda.stream(slot.stream):
@@ -234,9 +267,10 @@ class Server:
         slot.req = None
         return req
 
-    def run(self, requests: list[Request], versions: list[tuple[float, TableVersion]] | None = None,
+    def run(self, requests: list[Request], versions: list[tuple[float, TableVersion | InsertBatch]] | None = None,
             idle_sleep: float = 0.0) -> list[Request]:
-        """Serve `requests` at their arrival times (seconds from now); install table versions at their times."""
+        """Serve `requests` at their arrival times (seconds from now); install table versions (or insert rows) at
+        their times.  A request's row range is clipped to the rows of the version it is answered on."""
         versions = sorted(versions or [], key=lambda v: v[0])
         pending: list[Request] = []
         finished: list[Request] = []
@@ -245,7 +279,10 @@ class Server:
         while len(finished) < len(requests):
             now = self.now()
             while vi < len(versions) and versions[vi][0] <= now:
-                self.install(versions[vi][1])
+                if isinstance(versions[vi][1], InsertBatch):
+                    self.insert(versions[vi][1])
+                else:
+                    self.install(versions[vi][1])
                 vi += 1
             while i < len(requests) and requests[i].arrival <= now:
                 pending.append(requests[i])

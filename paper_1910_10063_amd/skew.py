@@ -41,13 +41,23 @@ EXPORTED = ("skew_last_error", "skew_workspace_bytes", "build_skew_layout", "fk_
             "skew_query_status", "skew_profile_enable", "skew_profile_report", "skew_max_hot_rows",
             "skew_max_hot_groups", "materialize_column", "select_fact_rows", "heavy_hitter_counts", "skew_max_hot",
             "cache_model_hit_rate", "star_join_batch", "star_join_autotune", "stream_probe",
-            "fk_join_aggregate_noalloc")
+            "fk_join_aggregate_noalloc", "skew_join_hot_rows", "skew_join_choose", "skew_group_choose",
+            "append_skew_layout")
 
 
 class StarTuning(ctypes.Structure):
     """skew_star_tuning of include/skew.h."""
     _fields_ = [("prod_hot_rows", ctypes.c_int32), ("cust_hot_rows", ctypes.c_int32),
                 ("tile_rows", ctypes.c_int32), ("blocks", ctypes.c_int32)]
+
+
+class Choice(ctypes.Structure):
+    _fields_ = [("hot_rows", ctypes.c_int32), ("partitioned", ctypes.c_int32), ("cold_share", ctypes.c_double),
+                ("l2_hit", ctypes.c_double), ("bytes_single", ctypes.c_double),
+                ("bytes_partitioned", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class SkewError(RuntimeError):
@@ -84,6 +94,14 @@ def load_library(path: str = LIB_PATH):
     lib.skew_query_status.restype = ctypes.c_int
     lib.skew_max_hot_rows.argtypes = [I32]
     lib.skew_max_hot_rows.restype = I32
+    lib.append_skew_layout.argtypes = [I32, I32, P, P, P, P, P, P, P, P, I64, P, P]
+    lib.append_skew_layout.restype = ctypes.c_int
+    lib.skew_join_choose.argtypes = [P, I32, I64, I32, P, P, SZ, P]
+    lib.skew_join_choose.restype = ctypes.c_int
+    lib.skew_group_choose.argtypes = [P, I32, I64, P, P, SZ, P]
+    lib.skew_group_choose.restype = ctypes.c_int
+    lib.skew_join_hot_rows.argtypes = [I64, I32, I32, I32, SZ]
+    lib.skew_join_hot_rows.restype = I32
     lib.skew_max_hot_groups.argtypes = []
     lib.skew_max_hot_groups.restype = I32
     lib.skew_profile_enable.argtypes = [ctypes.c_int]
@@ -187,6 +205,41 @@ def build_skew_layout(fact_keys: torch.Tensor, n_keys: int, price: torch.Tensor 
                                  _ptr(perm), _ptr(rank), _ptr(cbr), _ptr(fr), _ptr(po), _ptr(co), _ptr(ws),
                                  ws.numel(), _stream(dev)))
     return Layout(perm, rank, cbr, fr, po, co)
+
+
+def append_skew_layout(L: "Layout", n_new: int, price: torch.Tensor | None = None, category: torch.Tensor | None = None,
+                       fact_keys_new: torch.Tensor | None = None, in_place: bool = False) -> tuple["Layout", torch.Tensor | None]:
+    """Index maintenance without a rebuild (Section 3.1): L (a layout of n_old dimension rows) extended to n_new rows
+    (the new ids become its least frequent items; price/category are the whole dimension, new rows at the end) and
+    the new fact keys recoded through it.  Returns the extended layout (new tensors; its fact_recoded is L's) and
+    the recoded new keys."""
+    lib = load_library()
+    n_old = L.perm.numel()
+    dev = L.perm.device
+    perm = torch.empty(n_new, dtype=torch.int32, device=dev)
+    rank = torch.empty(n_new, dtype=torch.int32, device=dev)
+    cbr = torch.empty(n_new, dtype=torch.int32, device=dev)
+    perm[:n_old].copy_(L.perm)
+    rank[:n_old].copy_(L.rank)
+    cbr[:n_old].copy_(L.counts_by_rank)
+    po = co = None
+    if price is not None:
+        _need(price, torch.int32, "price")
+        po = torch.empty(n_new, dtype=torch.int32, device=dev)
+        po[:n_old].copy_(L.price)
+    if category is not None:
+        _need(category, torch.int8, "category")
+        co = torch.empty(n_new, dtype=torch.int8, device=dev)
+        co[:n_old].copy_(L.category)
+    fr = None
+    nf = 0
+    if fact_keys_new is not None:
+        _need(fact_keys_new, torch.int32, "fact_keys_new")
+        nf = fact_keys_new.numel()
+        fr = fact_keys_new if in_place else torch.empty_like(fact_keys_new)
+    _check(lib.append_skew_layout(n_old, n_new, _ptr(perm), _ptr(rank), _ptr(cbr), _ptr(price), _ptr(category),
+                                  _ptr(po), _ptr(co), _ptr(fact_keys_new), nf, _ptr(fr), _stream(dev)))
+    return Layout(perm, rank, cbr, L.fact_recoded, po, co), fr
 
 
 def fk_join_aggregate(fact_keys: torch.Tensor, price: torch.Tensor, category: torch.Tensor, cat_lt: int,
@@ -415,6 +468,46 @@ def max_hot_rows(group_by_category: bool) -> int:
     if v < 0:
         _check(v)
     return int(v)
+
+
+def join_hot_rows(n_fact: int, n_rows: int, group_by_category: bool, hot_rows: int = SKEW_HOT_AUTO,
+                  ws: torch.Tensor | None = None) -> int:
+    """The hot prefix fk_join_aggregate uses with these arguments (ws: the workspace it is given; None: one of
+    SKEW_OP_JOIN size)."""
+    lib = load_library()
+    nb = ws.numel() if ws is not None else workspace_bytes(SKEW_OP_JOIN, n_fact, n_rows)
+    v = lib.skew_join_hot_rows(n_fact, n_rows, 1 if group_by_category else 0, int(hot_rows), nb)
+    if v < 0:
+        _check(v)
+    return int(v)
+
+
+def join_choose(counts_by_rank: torch.Tensor, n_fact: int, group_by_category: bool,
+                ws: torch.Tensor | None = None) -> dict:
+    """The library's threshold prior for fk_join_aggregate on a layout (its counts_by_rank): hot_rows, form and the
+    modelled quantities."""
+    lib = load_library()
+    _need(counts_by_rank, torch.int32, "counts_by_rank")
+    n = counts_by_rank.numel()
+    if ws is None:
+        ws = workspace(SKEW_OP_CACHE_MODEL, 0, n, counts_by_rank.device)
+    c = Choice()
+    _check(lib.skew_join_choose(_ptr(counts_by_rank), n, n_fact, 1 if group_by_category else 0, ctypes.byref(c),
+                                _ptr(ws), ws.numel(), _stream(counts_by_rank.device)))
+    return c.as_dict()
+
+
+def group_choose(counts_by_rank: torch.Tensor, n_fact: int, ws: torch.Tensor | None = None) -> dict:
+    """The library's threshold prior for group_aggregate on a layout of its group keys."""
+    lib = load_library()
+    _need(counts_by_rank, torch.int32, "counts_by_rank")
+    n = counts_by_rank.numel()
+    if ws is None:
+        ws = workspace(SKEW_OP_CACHE_MODEL, 0, n, counts_by_rank.device)
+    c = Choice()
+    _check(lib.skew_group_choose(_ptr(counts_by_rank), n, n_fact, ctypes.byref(c), _ptr(ws), ws.numel(),
+                                 _stream(counts_by_rank.device)))
+    return c.as_dict()
 
 
 def max_hot_groups() -> int:

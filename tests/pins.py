@@ -238,6 +238,36 @@ def pin_stale_layout(orc):
         assert (s == s2).all() and (c == c2).all()
 
 
+def pin_append_layout(orc, seeds=range(10)):
+    """Index maintenance (Section 3.1): dimension rows appended after the build become the least frequent items
+    and fact rows inserted afterwards are recoded through the extended index.  The extended layout must still be a
+    bijection whose inverse is the rank form, and the join over the recoded facts and the permuted, extended
+    dimension must equal a nested-loop join on key values over the original rows."""
+    for seed in seeds:
+        rng = np.random.default_rng(500 + seed)
+        n_old = int(rng.integers(1, 7))
+        n_new = n_old + int(rng.integers(0, 4))
+        price = rng.integers(-50, 10000, n_new).astype(np.int32)
+        cat = rng.integers(-3, 19, n_new).astype(np.int8)
+        old = rng.integers(0, n_old, int(rng.integers(0, 15))).astype(np.int32)
+        add = rng.integers(0, n_new, int(rng.integers(0, 15))).astype(np.int32)
+        L = orc.build_layout(old, n_old, price[:n_old], cat[:n_old])
+        perm, rank, pn, cn, add_n, inv = orc.append_layout(L, n_new, price, cat, add)
+        assert inv == 0
+        assert sorted(perm.tolist()) == list(range(n_new)), seed
+        assert all(rank[perm[r]] == r for r in range(n_new)), seed
+        assert all(rank[k] >= n_old for k in range(n_old, n_new)), seed  # appended ids rank after every old one
+        assert (perm[:n_old] == L.perm).all() and (rank[:n_old] == L.rank).all(), seed  # no reorganisation
+        rows = [(int(k), int(price[k]), int(cat[k])) for k in rng.permutation(n_new)]
+        facts = np.concatenate([old, add])
+        recoded = np.concatenate([L.fact_recoded, add_n])
+        for cat_lt in (4, 16):
+            for by in (False, True):
+                s, c = orc.fk_join_aggregate(recoded, pn, cn, cat_lt, by)
+                bs, bc = nested_loop_join_aggregate(facts.tolist(), rows, cat_lt, by)
+                assert s.tolist() == bs and c.tolist() == bc, (seed, cat_lt, by)
+
+
 # ---------------------------------------------------------------------------
 # Operator variants (Section 4.1): materialization, selection, heavy hitters
 # ---------------------------------------------------------------------------
@@ -458,5 +488,6 @@ def pin_star_join(orc, seeds=range(10)):
 
 
 ALL_PINS = [pin_fk_bruteforce, pin_fk_special_cases, pin_group_bruteforce, pin_layout_bruteforce, pin_fig2,
-            pin_layout_invariants, pin_invariance_all_layouts, pin_stale_layout, pin_materialize, pin_select,
+            pin_layout_invariants, pin_invariance_all_layouts, pin_stale_layout, pin_append_layout, pin_materialize,
+            pin_select,
             pin_heavy_hitters, pin_cache_model, pin_star_join]

@@ -277,3 +277,30 @@ def _join_noalloc(lib, **kw):
 ])
 def test_join_noalloc_rejects(lib, kw, code):
     assert _join_noalloc(lib, **kw) == code
+
+
+def test_choose_rejects(lib):
+    c = skew.Choice()
+    assert lib.skew_join_choose(NULL, 10, 100, 1, ctypes.byref(c), WS, 1 << 20, S) == skew.SKEW_EINVAL
+    assert lib.skew_join_choose(A, 0, 100, 1, ctypes.byref(c), WS, 1 << 20, S) == skew.SKEW_EINVAL
+    assert lib.skew_join_choose(A, 10, 100, 2, ctypes.byref(c), WS, 1 << 20, S) == skew.SKEW_EINVAL
+    assert lib.skew_join_choose(A, 10, 100, 1, ctypes.byref(c), WS_MIS, 1 << 20, S) == skew.SKEW_EINVAL
+    assert lib.skew_group_choose(A, 10, -1, ctypes.byref(c), WS, 1 << 20, S) == skew.SKEW_EINVAL
+    assert lib.skew_group_choose(MIS, 10, 100, ctypes.byref(c), WS, 1 << 20, S) == skew.SKEW_EINVAL
+    assert lib.skew_join_hot_rows(10, 0, 1, -1, 0) == skew.SKEW_EINVAL
+
+
+def test_append_rejects(lib):
+    def app(**kw):
+        a = dict(n_old=10, n_new=12, perm=A, rank=A2, cbr=NULL, price=NULL, cat=NULL, po=NULL, co=NULL, keys=A,
+                 nf=5, out=A2)
+        a.update(kw)
+        return lib.append_skew_layout(a["n_old"], a["n_new"], a["perm"], a["rank"], a["cbr"], a["price"], a["cat"],
+                                      a["po"], a["co"], a["keys"], a["nf"], a["out"], S)
+    assert app(n_old=0) == skew.SKEW_EINVAL
+    assert app(n_new=9) == skew.SKEW_EINVAL
+    assert app(nf=-1) == skew.SKEW_EINVAL
+    assert app(perm=NULL) == skew.SKEW_EINVAL
+    assert app(price=A) == skew.SKEW_EINVAL  # price without its output
+    assert app(keys=NULL) == skew.SKEW_EINVAL
+    assert app(out=MIS) == skew.SKEW_EINVAL

@@ -176,3 +176,37 @@ def test_recode_crowded_low_keys(in_place):
     ref = oracle.build_layout(fact, N)
     L = skew.build_skew_layout(to_dev(fact), N, in_place=in_place)
     check(L, ref)
+
+
+# ---------------------------------------------------------------------------
+# Index maintenance without a rebuild (Section 3.1): dimension rows appended
+# after the build become the least frequent items and new fact rows are
+# recoded through the extended index.  Every array equals the oracle's; the
+# join over the old and new recoded facts equals the join over the original
+# rows.  A batch of 2^24 + 5 new keys takes the recode with the LDS table.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n_add_rows,n_add_facts", [(0, 1000), (5000, 2_000_003), (1, 1 << 24 | 5)])
+def test_append_layout(n_add_rows, n_add_facts):
+    k, N_old, F_old = 1, 100_000, 2_000_000
+    say(f"append layout +{n_add_rows} rows +{n_add_facts} facts")
+    N_new = N_old + n_add_rows
+    h = W.host_join_inputs(k, N_new, F_old, 1.0)
+    rng = np.random.default_rng(77 + n_add_rows)
+    old = h["fact"] % N_old  # the column the layout was built on references the old rows only
+    add = np.where(rng.random(n_add_facts) < 0.5, rng.integers(0, N_new, n_add_facts),
+                   h["fact"][rng.integers(0, F_old, n_add_facts)] % N_new).astype(np.int32)
+    ref = oracle.build_layout(old, N_old, h["price"][:N_old], h["category"][:N_old])
+    perm, rank, pn, cn, add_n, inv = oracle.append_layout(ref, N_new, h["price"], h["category"], add)
+    assert inv == 0
+    d_old = to_dev(old)
+    L = skew.build_skew_layout(d_old, N_old, to_dev(h["price"][:N_old]), to_dev(h["category"][:N_old]))
+    L2, add_d = skew.append_skew_layout(L, N_new, to_dev(h["price"]), to_dev(h["category"]), to_dev(add))
+    assert (host(L2.perm) == perm).all() and (host(L2.rank) == rank).all()
+    assert (host(L2.price) == pn).all() and (host(L2.category) == cn).all()
+    assert (host(L2.counts_by_rank)[N_old:] == 0).all()
+    assert (host(add_d) == add_n).all()
+    facts = np.concatenate([old, add])
+    es, ec = oracle.fk_join_aggregate(facts, h["price"], h["category"], 16, True)
+    keys = torch.cat([L.fact_recoded, add_d])
+    gs, gc = skew.fk_join_aggregate(keys, L2.price, L2.category, 16, True, hot_rows=skew.SKEW_HOT_AUTO)
+    assert (host(gs) == es).all() and (host(gc) == ec).all()

@@ -87,3 +87,57 @@ def test_model_edges():
     sk = skew.cache_model_hit_rate(cbr, 50, values_per_line=16)
     idn = skew.cache_model_hit_rate(cbr, 50, values_per_line=16, rank=torch.from_numpy(rank).to(DEV))
     assert sk >= idn
+
+
+# ---------------------------------------------------------------------------
+# Threshold prior: the choice follows from the frequencies by its stated rule
+# (checked on the host from the oracle's layout), its L2 hit rate is the
+# model's on the ranks past the threshold, and the query run with the choice
+# gives the oracle's answer.
+# ---------------------------------------------------------------------------
+def _check_choice(ch, cbr, F, cap, row_threshold, per_line):
+    t = 0
+    while t < min(cap, cbr.size) and cbr[t] >= row_threshold:
+        t += 1
+    assert ch["hot_rows"] == t, (ch, t)
+    assert abs(ch["cold_share"] - (F - cbr[:t].sum()) / F) < 1e-12
+    if t < cbr.size:
+        want = oracle.cache_model(oracle.line_frequencies(cbr[t:], per_line), 32768)
+        assert abs(ch["l2_hit"] - want) < 1e-6, (ch["l2_hit"], want)
+    assert ch["partitioned"] == (1 if ch["bytes_partitioned"] < ch["bytes_single"] else 0)
+
+
+@pytest.mark.parametrize("s", [0.0, 1.0, 1.5])
+def test_join_choice(s):
+    N, F = 1_000_000, 20_000_003
+    say(f"join threshold prior N={N} F={F} s={s}")
+    h = W.host_join_inputs(2, N, F, s)
+    ref = oracle.build_layout(h["fact"], N, h["price"], h["category"])
+    d = {n: torch.from_numpy(h[n]).to(DEV) for n in ("fact", "price", "category")}
+    L = skew.build_skew_layout(d["fact"], N, d["price"], d["category"])
+    ch = skew.join_choose(L.counts_by_rank, F, True)
+    # one round of 256 workgroups: a row is kept when its count reaches 4 * 256 / 13 bytes
+    _check_choice(ch, ref.counts_by_rank.astype(np.int64), F, skew.max_hot_rows(True), 4.0 * 256 / 13.0, 32)
+    if s == 0.0:
+        assert ch["hot_rows"] == 0  # about 20 keys per row: no row pays for its copies
+    ws = skew.workspace(skew.SKEW_OP_JOIN if ch["partitioned"] else skew.SKEW_OP_JOIN_SINGLE_PASS, F, N, DEV)
+    es, ec = oracle.fk_join_aggregate(h["fact"], h["price"], h["category"], 16, True)
+    gs, gc = skew.fk_join_aggregate(L.fact_recoded, L.price, L.category, 16, True, hot_rows=ch["hot_rows"], ws=ws)
+    assert (host(gs) == es).all() and (host(gc) == ec).all()
+
+
+def test_group_choice():
+    M, F = 100_000, 10_000_001
+    say(f"group threshold prior M={M} F={F}")
+    h = W.host_group_inputs(3, M, F, 1.1)
+    ref = oracle.build_layout(h["keys"], M)
+    L = skew.build_skew_layout(torch.from_numpy(h["keys"]).to(DEV), M)
+    ch = skew.group_choose(L.counts_by_rank, F)
+    # one round of 256 workgroups: a group is kept when its count reaches 32 * 256 / 16
+    _check_choice(ch, ref.counts_by_rank.astype(np.int64), F, skew.max_hot_groups(), 32 * 256 / 16.0, 16)
+    ws = skew.workspace(skew.SKEW_OP_GROUP if ch["partitioned"] else skew.SKEW_OP_GROUP_SINGLE_PASS, F, M, DEV)
+    es, ec, _ = oracle.group_aggregate(h["keys"], h["vals"], M)
+    gs, gc = skew.group_aggregate(L.fact_recoded, torch.from_numpy(h["vals"]).to(DEV), M,
+                                  hot_groups=ch["hot_rows"] if ch["hot_rows"] > 0 else skew.SKEW_HOT_NONE,
+                                  perm=L.perm, ws=ws)
+    assert (host(gs) == es).all() and (host(gc) == ec).all()

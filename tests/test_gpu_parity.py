@@ -444,3 +444,34 @@ def test_join_dimension_columns_at_any_alignment(F, poff, coff):
         for t in (0, 1000, skew.SKEW_HOT_AUTO):
             s, c = skew.fk_join_aggregate(keys, pv, cv, cat_lt, by_cat, hot_rows=t)
             assert (host(s) == es).all() and (host(c) == ec).all(), (cat_lt, t)
+
+
+# ---------------------------------------------------------------------------
+# Cold-key buckets of the partitioned join under inputs that defeat the
+# bucket plan: keys sorted (every tile falls into a few slices), every key
+# in one slice, and runs of hot keys between runs of keys spread over all
+# slices.  Keys that find no room are gathered; every answer stays exact.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", ["sorted", "one_slice", "runs"])
+def test_join_bucket_overflow_inputs(shape):
+    rng = np.random.default_rng({"sorted": 61, "one_slice": 62, "runs": 63}[shape])
+    N, F = 1_000_000, (1 << 22) + 777
+    say(f"join buckets shape={shape} N={N} F={F}")
+    price = rng.integers(1, 10001, N).astype(np.int32)
+    cat = rng.integers(0, 16, N).astype(np.int8)
+    if shape == "sorted":
+        fact = np.sort(rng.integers(0, N, F)).astype(np.int32)
+    elif shape == "one_slice":
+        fact = rng.integers(200_000, 200_000 + 32768, F).astype(np.int32)
+    else:
+        fact = rng.integers(0, N, F).astype(np.int32)
+        run = np.arange(F) // 50_000 % 2 == 0
+        fact[run] = rng.integers(0, 1000, int(run.sum()))
+    ws = skew.workspace(skew.SKEW_OP_JOIN, F, N, DEV)
+    fd, pd, cd = to_dev(fact), to_dev(price), to_dev(cat)
+    for by_cat, cat_lt in ((True, 16), (False, 4)):
+        es, ec = oracle.fk_join_aggregate(fact, price, cat, cat_lt, by_cat)
+        for t in (0, 1000, skew.SKEW_HOT_AUTO):
+            s, c = skew.fk_join_aggregate(fd, pd, cd, cat_lt, by_cat, hot_rows=t, ws=ws)
+            assert (host(s) == es).all() and (host(c) == ec).all(), (by_cat, t)
+    assert skew.query_status(ws) == skew.SKEW_OK

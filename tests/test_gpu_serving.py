@@ -109,3 +109,39 @@ def test_drift_rebuild_keeps_answers(tables):
         np.testing.assert_array_equal(gc, ec, err_msg=f"request {rid} (version {r.version}, {r.layout}): COUNT")
     v2 = [r for r in done.values() if r.version == 2]
     assert any(r.layout == "skew" for r in v2)
+
+
+def test_insert_served_on_the_layout(tables):
+    say("serving: rows inserted at 0.2 s, recoded through the current layout; every request vs the oracle")
+    n_ins = 3_000_000
+    rng = np.random.default_rng(31)
+    h1 = tables["h1"]
+    pick = rng.integers(0, F, n_ins)
+    ins_keys, ins_vals = h1["keys"][pick], rng.integers(0, 1001, n_ins).astype(np.int32)
+    batch = serving.InsertBatch(torch.from_numpy(ins_keys).to(DEV), torch.from_numpy(ins_vals).to(DEV))
+    t1 = tables["t1"]
+    srv = serving.Server(t1, 4, 4_000_000)
+    serving.start_layout(srv, t1)
+    arr = serving.poisson_arrivals(200.0, 0.4, 9)
+    reqs = serving.make_requests(arr, F + n_ins, 10_000, 4_000_000, 9)
+    for r in reqs:
+        r.out = (torch.full((M,), -7, dtype=torch.int64, device=DEV), torch.full((M,), -7, dtype=torch.int64,
+                                                                                   device=DEV))
+    torch.cuda.synchronize()
+    done = {r.rid: r for r in srv.run(reqs, [(0.2, batch)])}
+    torch.cuda.synchronize()
+    ev = [e for e in srv.events if e["event"] == "insert"]
+    assert len(ev) == 1 and ev[0]["served_on"] == "skew"
+    assert not any(e["event"] == "layout_ready" for e in srv.events)  # no rebuild
+    keys2 = np.concatenate([h1["keys"], ins_keys])
+    vals2 = np.concatenate([h1["vals"], ins_vals])
+    assert {r.version for r in done.values()} == {1, 2}
+    for rid in sorted(done):
+        r = done[rid]
+        assert r.layout == "skew"
+        kk, vv = (h1["keys"], h1["vals"]) if r.version == 1 else (keys2, vals2)
+        es, ec, _ = oracle.group_aggregate(kk[r.start:r.start + r.rows], vv[r.start:r.start + r.rows], M)
+        gs, gc = arrays(r)
+        np.testing.assert_array_equal(gs, es, err_msg=f"request {rid} (version {r.version}): SUM")
+        np.testing.assert_array_equal(gc, ec, err_msg=f"request {rid} (version {r.version}): COUNT")
+    assert any(r.version == 2 and r.start + r.rows > F for r in done.values())  # some answer reads inserted rows

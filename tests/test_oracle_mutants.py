@@ -38,6 +38,9 @@ MUTANTS = {
     "model_no_repeat_term": ("    if (n > 1.0) rep += n - 1.0;", "    if (n > 1.0) rep += n;"),
     "model_cdf_exponent": ("hit += f[i] * (1.0 - pow(1.0 - f[i], (double)lo));", "hit += f[i] * (1.0 - pow(1.0 - f[i], (double)S));"),
     "model_scale_dropped": ("  const double scale = k / (1.0 - f[i]);", "  const double scale = k;"),
+    "append_price_shifted": ("    if (price && price_new) price_new[i] = price[i];", "    if (price && price_new) price_new[i] = price[i - 1];"),
+    "append_rank_first": ("    rank[i] = i;\n    if (price && price_new)", "    rank[i] = 0;\n    if (price && price_new)"),
+    "append_perm_reversed": ("    perm[i] = i;\n    rank[i] = i;", "    perm[i] = n_new - 1 - (i - n_old);\n    rank[i] = i;"),
     "star_filter_inverted": ("    if (!(cust_attr[u] < cust_lt)) continue;", "    if (cust_attr[u] < cust_lt) continue;"),
     "star_customer_as_product": ("    const int32_t g = category[p];\n    if (g < 0 || g >= 16) continue;\n    sum[g] += (int64_t)price[p];",
                                  "    const int32_t g = category[p];\n    if (g < 0 || g >= 16) continue;\n    sum[g] += (int64_t)price[u < n_prod ? u : p];"),
