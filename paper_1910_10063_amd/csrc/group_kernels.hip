@@ -750,11 +750,14 @@ hipError_t launch_group(const int32_t *keys, const int32_t *vals, int64_t n_fact
         if (e == hipSuccess) e = launch_partition_plan(tab, Q, pl.blocks, s);
         stage_end(st, s);
         st = stage_begin("group_scatter", s);
+        // with no or few privatised groups, slice 0 of a frequency-ordered layout holds most partitioned rows
+        const bool combine0 = t < kCombineBelow;
         if (e == hipSuccess && np)
-          e = launch_partition_scatter_narrow(tab_n, np, pl.blocks, seg_n, pl.seg_cap, pl.wshift, items_v, s);
+          e = launch_partition_scatter_narrow(tab_n, np, pl.blocks, seg_n, pl.seg_cap, pl.wshift, items_v, s,
+                                              combine0);
         if (e == hipSuccess)
           e = launch_partition_scatter(tab_p, pl.slices, pl.blocks, seg_k, seg_v, pl.seg_cap, 0, pl.wshift, items_k,
-                                       items_v, s);
+                                       items_v, s, combine0);
         stage_end(st, s);
         if (e != hipSuccess) return e;
         st = stage_begin("group_slice", s);

@@ -45,9 +45,7 @@ __global__ void join_pack_kernel(const int32_t *__restrict__ price, const int8_t
 
 constexpr int kJoinVecs = 4;  // 16-byte key vectors per lane per batch
 constexpr int64_t kJoinAutoMinHot = 8192;  // smallest automatic prefix of the single pass
-// Pass 1 counts the keys of slice 0 once per slot below this prefix: on a frequency-ordered layout slice 0
-// then holds more than a sixth of the cold keys (at Zipf 1), and one counter would take many lanes per slot.
-constexpr int32_t kCombineBelow = 16384;
+
 
 // Accumulators.  GROUPS == 16: every lane owns one 64-bit bin per group in
 // LDS, shared by the 16 waves of the workgroup through LDS atomics (two lanes
@@ -349,7 +347,9 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
   o.t = (uint32_t)t_lds;
   o.wshift = wshift;
   o.sink = (uint32_t)P + lane_id();
-  o.combine0 = t_lds < kCombineBelow;  // below it slice 0 takes a large share of the cold keys
+  // with no or a small hot prefix, slice 0 of a frequency-ordered layout takes most cold keys: its lanes are
+  // counted once per slot instead of queueing on one counter
+  o.combine0 = t_lds < kCombineBelow;
   const uint32_t tclamp = t_lds > 0 ? (uint32_t)t_lds - 1 : 0u;
   const Tail tail{(uint32_t)tail_start, record_buffer(words, (uint32_t)n_rows)};
 
@@ -677,7 +677,7 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
     st = stage_begin("join_scatter", s);
     if (e == hipSuccess)
       e = launch_partition_scatter(tab, pl.slices, pl.blocks, seg, nullptr, pl.seg_cap, t, pl.wshift, items, nullptr,
-                                   s);
+                                   s, t < kCombineBelow);
     stage_end(st, s);
     if (e != hipSuccess) return e;
     st = stage_begin("join_slice", s);

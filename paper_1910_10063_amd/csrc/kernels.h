@@ -45,15 +45,19 @@ hipError_t launch_exclusive_scan(uint32_t *a, int64_t n, uint32_t *total, uint32
 hipError_t launch_partition_plan(const SliceTables &tab, int32_t P, int32_t B, hipStream_t s);
 // Move every block's cold items into slice order, as 2-byte offsets inside
 // their slice (plus the values when seg_vals is given).
+// combine0: blocks whose items are mostly in slice 0 (a frequency-ordered layout with a small or no hot
+// prefix) rank those items with one LDS add per load.
+constexpr int32_t kCombineBelow = 2048;  // hot prefixes below which the partitioned forms combine slice 0
 hipError_t launch_partition_scatter(const SliceTables &tab, int32_t P, int32_t B, const int32_t *seg_keys,
                                     const int32_t *seg_vals, int64_t seg_cap, int32_t t, int32_t wshift,
-                                    uint16_t *out_local, int32_t *out_vals, hipStream_t s);
+                                    uint16_t *out_local, int32_t *out_vals, hipStream_t s, bool combine0 = false);
 // The group-by's narrow records: group << kGroupNarrowShift | value in the
 // segments, (group offset inside its slice) << kGroupNarrowShift | value in
 // slice order (out_items), slices of 1 << wshift groups from group 0.
 constexpr int kGroupNarrowShift = 12;
 hipError_t launch_partition_scatter_narrow(const SliceTables &tab, int32_t P, int32_t B, const int32_t *seg_recs,
-                                           int64_t seg_cap, int32_t wshift, int32_t *out_items, hipStream_t s);
+                                           int64_t seg_cap, int32_t wshift, int32_t *out_items, hipStream_t s,
+                                           bool combine0 = false);
 
 // Partitioned key histogram (large fact columns, at most kMaxSlices slices of
 // 32768 keys).  counts must be zeroed; keys outside [0, n_keys) set *flag.

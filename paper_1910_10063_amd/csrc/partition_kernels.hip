@@ -157,7 +157,7 @@ constexpr int kScatterTile = kScatterThreads * kScatterPer;
 
 size_t scatter_lds_bytes(bool pairs) { return (size_t)kScatterTile * 4 * (pairs ? 2 : 1); }
 
-template <bool PAIRS, bool NARROW = false>
+template <bool PAIRS, bool NARROW = false, bool COMBINE0 = false>
 __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
     const int32_t *__restrict__ seg_keys, const int32_t *__restrict__ seg_vals, int64_t seg_cap,
     const uint32_t *__restrict__ seg_count, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ slice_off,
@@ -171,10 +171,13 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
   const int b = blockIdx.x, B = gridDim.x, tid = threadIdx.x;
   for (int p = tid; p < P; p += blockDim.x) run[p] = slice_off[p] + hist[(int64_t)p * B + b];
   const uint32_t cnt = seg_count[b];
-  // this block's items of slice 0 (the row scan left exclusive prefixes over the blocks): when they are a
-  // quarter of its segment or more, the lanes of a load that fall into slice 0 take their ranks together
-  const uint32_t n0 = (b + 1 < B ? hist[b + 1] : slice_off[1] - slice_off[0]) - hist[b];
-  const bool combine0 = 4ull * n0 >= (uint64_t)cnt && cnt > 0;
+  // With COMBINE0, when this block's items of slice 0 (the row scan left exclusive prefixes over the blocks)
+  // are half of its segment or more, the lanes of a load that fall into slice 0 take their ranks together.
+  bool combine0 = false;
+  if (COMBINE0) {
+    const uint32_t n0 = (b + 1 < B ? hist[b + 1] : slice_off[1] - slice_off[0]) - hist[b];
+    combine0 = 2ull * n0 >= (uint64_t)cnt && cnt > 0;
+  }
   // segments start 16-byte aligned and hold a multiple of 4 slots, so every
   // vector that starts below cnt lies inside the segment
   const i32x4 *sk = reinterpret_cast<const i32x4 *>(seg_keys + (int64_t)b * seg_cap);
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_kernel(
         // rank among the tile's items of the slice; the lanes whose items fall into slice 0 (the densest
         // one on a frequency-ordered layout) take consecutive ranks with one LDS add
         const uint32_t sl = slice_of(kv[j]);
-        if (combine0) {
+        if (COMBINE0 && combine0) {
           const bool z = i < n && sl == 0;
           const uint64_t mz = __ballot(z);
           uint32_t base0 = 0;
@@ -660,30 +663,36 @@ hipError_t launch_partition_plan(const SliceTables &tab, int32_t P, int32_t B, h
 
 hipError_t launch_partition_scatter(const SliceTables &tab, int32_t P, int32_t B, const int32_t *seg_keys,
                                     const int32_t *seg_vals, int64_t seg_cap, int32_t t, int32_t wshift,
-                                    uint16_t *out_local, int32_t *out_vals, hipStream_t s) {
+                                    uint16_t *out_local, int32_t *out_vals, hipStream_t s, bool combine0) {
+  auto go = [&](auto kernel, bool pairs) {
+    const size_t lds = scatter_lds_bytes(pairs);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL(kernel, dim3(B), dim3(kScatterThreads), lds, s, seg_keys, seg_vals, seg_cap, tab.seg_count,
+                       tab.hist, tab.slice_off, P, t, wshift, out_local, out_vals);
+  };
   if (seg_vals) {
-    const size_t lds = scatter_lds_bytes(true);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(scatter_kernel<true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(scatter_kernel<true>, dim3(B), dim3(kScatterThreads), lds, s, seg_keys, seg_vals, seg_cap,
-                       tab.seg_count, tab.hist, tab.slice_off, P, t, wshift, out_local, out_vals);
+    if (combine0) go(scatter_kernel<true, false, true>, true);
+    else go(scatter_kernel<true, false, false>, true);
   } else {
-    const size_t lds = scatter_lds_bytes(false);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(scatter_kernel<false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(scatter_kernel<false>, dim3(B), dim3(kScatterThreads), lds, s, seg_keys, seg_vals, seg_cap,
-                       tab.seg_count, tab.hist, tab.slice_off, P, t, wshift, out_local, out_vals);
+    if (combine0) go(scatter_kernel<false, false, true>, false);
+    else go(scatter_kernel<false, false, false>, false);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_partition_scatter_narrow(const SliceTables &tab, int32_t P, int32_t B, const int32_t *seg_recs,
-                                           int64_t seg_cap, int32_t wshift, int32_t *out_items, hipStream_t s) {
-  const size_t lds = scatter_lds_bytes(false);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(scatter_kernel<false, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((scatter_kernel<false, true>), dim3(B), dim3(kScatterThreads), lds, s, seg_recs, nullptr, seg_cap,
-                     tab.seg_count, tab.hist, tab.slice_off, P, 0, wshift, nullptr, out_items);
+                                           int64_t seg_cap, int32_t wshift, int32_t *out_items, hipStream_t s,
+                                           bool combine0) {
+  auto go = [&](auto kernel) {
+    const size_t lds = scatter_lds_bytes(false);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL(kernel, dim3(B), dim3(kScatterThreads), lds, s, seg_recs, nullptr, seg_cap, tab.seg_count,
+                       tab.hist, tab.slice_off, P, 0, wshift, nullptr, out_items);
+  };
+  if (combine0) go(scatter_kernel<false, true, true>);
+  else go(scatter_kernel<false, true, false>);
   return hipGetLastError();
 }
 
