@@ -620,12 +620,12 @@ int32_t group_split_max_hot_groups(int32_t slices, const DeviceInfo &dev) {
 
 GroupPlan group_plan(int64_t n_fact, int32_t n_groups, const DeviceInfo &dev) {
   GroupPlan pl;
-  // at least 32 workgroups: every workgroup gets fewer than kPackMaxRows rows of a round
-  pl.blocks = dev.cu_count > 32 ? dev.cu_count : 32;
+  // at least 64 workgroups: every workgroup gets fewer than kPackMaxRows rows of a round
+  pl.blocks = dev.cu_count > 64 ? dev.cu_count : 64;
   pl.wshift = kGroupSliceShift;
   pl.slices = (int32_t)(((int64_t)n_groups + (1 << pl.wshift) - 1) >> pl.wshift);
-  pl.round = n_fact < kMaxRound ? n_fact : kMaxRound;
-  static_assert(kMaxRound / 32 + 64 < kPackMaxRows, "pass-1 bins must see fewer than 2^24 rows");
+  pl.round = n_fact < kGroupMaxRound ? n_fact : kGroupMaxRound;
+  static_assert(kGroupMaxRound / 64 + 64 < kPackMaxRows, "pass-1 bins must see fewer than 2^24 rows");
   // rows per workgroup (vector ranges round up by at most 4 rows per block,
   // plus the scalar head and tail), with a generous margin
   pl.seg_cap = 4 * (((pl.round + pl.blocks - 1) / pl.blocks + 64 + 3) / 4);

@@ -78,6 +78,7 @@ constexpr int kJoinSliceShift = 15;     // 32768 dimension words per LDS slice
 constexpr int kGroupSliceShift = 13;    // 8192 groups per LDS slice
 constexpr int64_t kMaxRound = 1LL << 28;         // rows per round of the partitioned form
 constexpr int64_t kJoinMaxRound = 1LL << 29;     // the join's rounds (fewer copies of each slice in pass 3)
+constexpr int64_t kGroupMaxRound = 1LL << 29;    // the group-by's rounds
 constexpr int64_t kPartitionMinFact = 1LL << 22;  // below this the single pass is used
 
 // Partitioned form: cold items of each round go through per-block segments,

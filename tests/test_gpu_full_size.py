@@ -106,6 +106,29 @@ def test_group_by_full_size():
     torch.cuda.empty_cache()
 
 
+def test_group_by_two_rounds():
+    """2^29 + 2^20 + 3 rows: a full round of the partitioned group-by and a ragged second one, on both layouts,
+    with the bench's values and with values up to 7e4 (cold rows as pairs, hot rows over 2^16 partitioned)."""
+    M, F, S = 1_000_000, (1 << 29) + (1 << 20) + 3, 1.1
+    say(f"group-by two rounds M={M} F={F} s={S}")
+    g = W.device_group_inputs(3, M, F, S, device=DEV)
+    L = skew.build_skew_layout(g["keys"], M)
+    keys_h = host(g["keys"])
+    ws = skew.workspace(skew.SKEW_OP_GROUP, F, M, DEV)
+    for scale in (1, 70):
+        vals = g["vals"] * scale
+        es, ec, inv = oracle.group_aggregate(keys_h, host(vals), M)
+        assert inv == 0
+        s, c = skew.group_aggregate(L.fact_recoded, vals, M, hot_groups=skew.SKEW_HOT_AUTO, perm=L.perm, ws=ws)
+        assert (host(s) == es).all() and (host(c) == ec).all(), f"skew layout, values x{scale}"
+        s, c = skew.group_aggregate(g["keys"], vals, M, hot_groups=0, ws=ws)
+        assert (host(s) == es).all() and (host(c) == ec).all(), f"identity layout, values x{scale}"
+        del vals
+    assert skew.query_status(ws) == skew.SKEW_OK
+    del g, L, ws
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("S", [0.0, 0.5, 1.5])
 def test_join_zipf_sweep_one_round(S):
     """The other exponents of the sweep on a 1e7-row dimension, 2^28 + 3 keys (a ragged tail)."""
