@@ -348,8 +348,10 @@ typedef struct {
  *   workspace                   >= skew_workspace_bytes(SKEW_OP_STAR, n_queries,
  *                               max(n_prod, n_cust)): packed product words
  *                               (4 bytes per row), a padded copy of the
- *                               segments, the work queue, and one bitmap of
- *                               min(n_cust, 2^20) bits per query.
+ *                               segments, the work queue, and one bitmap per
+ *                               query: over every customer row when the
+ *                               n_queries bitmaps take at most 1 GiB, else over
+ *                               min(n_cust, 2^20) rows.
  * Keys outside their dimension join nothing and set the error flag.
  */
 int star_join_batch(const int32_t *prod_keys, const int32_t *cust_keys, const int64_t *query_start,

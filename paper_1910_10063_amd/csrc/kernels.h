@@ -132,11 +132,14 @@ hipError_t launch_cache_model(const uint32_t *counts_by_rank, int32_t n_keys, co
 // ---- batched star join ----
 constexpr int32_t kMaxStarQueries = 4096;
 constexpr int32_t kStarMaxCustHot = 1 << 20;  // customer bitmap rows per query (128 KB)
+constexpr size_t kStarFullBitsBytes = (size_t)1 << 30;  // all queries' bitmaps over every customer row
 size_t star_lds_bytes(int32_t tp, int32_t tc, int32_t nq);
 int32_t star_bits_stride(int32_t tc);
+bool star_full_bits(int32_t n_cust, int32_t nq);
 int32_t star_max_prod_hot(int32_t tc, int32_t nq, const DeviceInfo &dev);
 int32_t star_max_cust_hot(int32_t nq, const DeviceInfo &dev);
 size_t star_workspace_bytes(int32_t n_prod, int32_t n_cust, int32_t nq);
+size_t star_workspace_bound(int32_t n_rows, int32_t nq);  // any n_prod, n_cust <= n_rows
 hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t *qstart, const int32_t *qlt,
                        int32_t nq, const int32_t *price, const int8_t *cat, int32_t n_prod, const int8_t *attr,
                        int32_t n_cust, int32_t tp, int32_t tc, int64_t tile_rows, int32_t blocks, int64_t *out_sum,

@@ -248,7 +248,7 @@ size_t skew_workspace_bytes(int op, int64_t n_fact, int32_t n_keys) {
     case SKEW_OP_CACHE_MODEL:
       return skew::kFlagBytes + round_up(skew::model_workspace_bytes(n_keys, 1));
     case SKEW_OP_STAR:
-      return skew::kFlagBytes + round_up(skew::star_workspace_bytes(n_keys, n_keys, (int32_t)n_fact));
+      return skew::kFlagBytes + round_up(skew::star_workspace_bound(n_keys, (int32_t)n_fact));
     case SKEW_OP_SELECT:
       return skew::kFlagBytes + round_up(skew::select_workspace_bytes(n_fact, n_keys, kPartBlocks));
     default:

@@ -9,7 +9,12 @@
 // filter's outcome, one bit per row, so a workgroup holds eight times more
 // hot customers than it would segments; every query has its own bitmap,
 // built before the batch kernel and staged into LDS when a workgroup moves on
-// to a tile of another query.  Every launch here is a kernel (no memset or
+// to a tile of another query.  When the bitmaps of all queries over every
+// customer row fit a fixed budget, they are built for every row, and a cold
+// customer row reads its bit from the query's bitmap in global memory (a
+// 2e6-row dimension is 250 KB of bits per query, against 2 MB of segments
+// shared by all queries, so the rows the queries read stay in L2 next to
+// more of the product words).  Every launch here is a kernel (no memset or
 // host copy), so the whole call can be captured in a HIP graph and replayed.
 #include "kernels.h"
 #include "profiler.h"
@@ -127,17 +132,23 @@ struct StarCtx {
   const uint32_t *chot;  // LDS: the current query's customer bitmap, rows [0, tc)
   uint32_t tc, tcclamp;  // tc in rows (bits), tcclamp in words
   rsrc_t cwords;         // all customer segments, four to a word (range-checked)
+  rsrc_t cbits;          // FULL: the current query's bitmap over every customer row (range-checked)
   uint32_t n_prod, n_cust;
 };
 
 // Whether customer row u < n_cust passes the query's filter: a bit of the
-// LDS bitmap for a hot row, the row's segment gathered and compared for a
-// cold one (the gather index is pushed out of range for hot rows, so they
-// cost no memory traffic).
+// LDS bitmap for a hot row; for a cold one, its bit of the query's bitmap in
+// global memory (FULL) or its segment, gathered and compared.  The gather
+// index is pushed out of range for hot rows, so they cost no memory traffic.
+template <bool FULL>
 __device__ __forceinline__ bool cust_pass(const StarCtx &x, uint32_t u, int32_t lt) {
   const bool hot = u < x.tc;
   const uint32_t wi = u >> 5;
   const uint32_t bl = x.chot[wi < x.tcclamp ? wi : x.tcclamp] >> (u & 31u);
+  if (FULL) {
+    const uint32_t wg = buffer_load_record(x.cbits, (int32_t)(hot ? 0xFFFFFFFFu : wi), 0, 0, 0);
+    return ((hot ? bl : wg >> (u & 31u)) & 1u) != 0u;
+  }
   const uint32_t wg = buffer_load_record(x.cwords, (int32_t)(hot ? 0xFFFFFFFFu : (u >> 2)), 0, 0, 0);
   const int32_t seg = (int32_t)(int8_t)(wg >> (8 * (u & 3u)));
   return hot ? (bl & 1u) != 0u : seg < lt;
@@ -180,8 +191,9 @@ __device__ __forceinline__ void star_slow(StarAcc &a, const StarCtx &x, uint32_t
 }
 
 // One row: product word if the customer passes, the sink bin otherwise.
+template <bool FULL>
 __device__ __forceinline__ void star_row(StarAcc &a, const StarCtx &x, uint32_t p, uint32_t u, int32_t lt) {
-  const bool pass = u < x.n_cust && cust_pass(x, u, lt);
+  const bool pass = u < x.n_cust && cust_pass<FULL>(x, u, lt);
   const uint32_t wp = prod_word(x, p, pass);
   const uint32_t w = pass ? wp : kValid;
   star_add(a, w);
@@ -210,6 +222,7 @@ __device__ __forceinline__ void star_flush(StarAcc &a) {
   __syncthreads();
 }
 
+template <bool FULL>
 __global__ __launch_bounds__(kStarThreads) void star_batch_kernel(
     const int32_t *__restrict__ pkeys, const int32_t *__restrict__ ukeys, const int64_t *__restrict__ qstart,
     const int32_t *__restrict__ qlt, int32_t nq, const uint32_t *__restrict__ tile_start, uint32_t *counter,
@@ -269,8 +282,9 @@ __global__ __launch_bounds__(kStarThreads) void star_batch_kernel(
     if (q != staged_q && tc > 0) {  // uniform: every thread has the same tile; the last tile's reads are done
       stage_words(chot, cbits, (int64_t)q * cstride, tc_bits_words);
       __syncthreads();
-      staged_q = q;
     }
+    if (FULL) x.cbits = record_buffer(cbits + (int64_t)q * cstride, (uint32_t)(((int64_t)n_cust + 31) / 32));
+    staged_q = q;
     const int64_t r0 = qstart[q] + (int64_t)(tile - lts[q]) * tile_rows;
     const int64_t r1 = r0 + tile_rows < qstart[q + 1] ? r0 + tile_rows : qstart[q + 1];
     const int32_t lt = qlt[q];
@@ -284,7 +298,7 @@ __global__ __launch_bounds__(kStarThreads) void star_batch_kernel(
     const int32_t *su = ukeys + base;
     walk_items<4, kStarVecs, kStarThreads, KeyPair>(
         (uint32_t)(r0 - base), (uint32_t)(r1 - base),
-        [&](uint32_t i) { star_row(a, x, (uint32_t)sp[i], (uint32_t)su[i], lt); },
+        [&](uint32_t i) { star_row<FULL>(a, x, (uint32_t)sp[i], (uint32_t)su[i], lt); },
         [&](uint32_t vi) { return KeyPair{load_stream4(bp + vi), load_stream4(bu + vi)}; },
         [&](const KeyPair(&kp)[kStarVecs], const bool(&valid)[kStarVecs]) {
           uint32_t w[4 * kStarVecs], p[4 * kStarVecs], u[4 * kStarVecs];
@@ -300,7 +314,7 @@ __global__ __launch_bounds__(kStarThreads) void star_batch_kernel(
 #pragma unroll
           for (int i = 0; i < 4 * kStarVecs; ++i) {
             const bool in_c = u[i] < x.n_cust;
-            pass[i] = valid[i / 4] && in_c && cust_pass(x, u[i], lt);
+            pass[i] = valid[i / 4] && in_c && cust_pass<FULL>(x, u[i], lt);
             const uint32_t wp = prod_word(x, p[i], pass[i]);
             w[i] = pass[i] ? wp : kValid;
             rare |= (uint32_t)((pass[i] && wp == 0u) || (valid[i / 4] && (!in_c || p[i] >= x.n_prod)));
@@ -345,7 +359,7 @@ size_t star_lds_bytes(int32_t tp, int32_t tc, int32_t nq) {
          (size_t)(nq + 1) * 4;
 }
 
-int32_t star_bits_stride(int32_t tc) { return (((tc + 31) / 32) + 3) & ~3; }
+int32_t star_bits_stride(int32_t tc) { return (int32_t)(((((int64_t)tc + 31) / 32) + 3) & ~(int64_t)3); }
 
 int32_t star_max_prod_hot(int32_t tc, int32_t nq, const DeviceInfo &dev) {
   const size_t fixed = star_lds_bytes(0, tc, nq) - 16 + kStaticReserve;
@@ -363,7 +377,16 @@ int32_t star_max_cust_hot(int32_t nq, const DeviceInfo &dev) {
 
 namespace {
 size_t seg_padded(int32_t n_cust) { return ((size_t)n_cust + 31) / 32 * 32; }
-size_t star_bits_words(int32_t n_cust) {
+}  // namespace
+
+bool star_full_bits(int32_t n_cust, int32_t nq) {
+  return (size_t)nq * (size_t)star_bits_stride(n_cust) * 4 <= kStarFullBitsBytes;
+}
+
+namespace {
+// words per query bitmap: every customer row when all bitmaps fit the budget, else the largest LDS prefix
+size_t star_bits_words(int32_t n_cust, int32_t nq) {
+  if (star_full_bits(n_cust, nq)) return (size_t)star_bits_stride(n_cust);
   return (size_t)star_bits_stride(n_cust < kStarMaxCustHot ? n_cust : kStarMaxCustHot);
 }
 }  // namespace
@@ -371,7 +394,18 @@ size_t star_bits_words(int32_t n_cust) {
 size_t star_workspace_bytes(int32_t n_prod, int32_t n_cust, int32_t nq) {
   auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
   return r((size_t)n_prod * 4) + r(seg_padded(n_cust) + 16) + r((size_t)(nq + 1) * 4) + r(16) +
-         r((size_t)nq * star_bits_words(n_cust) * 4);
+         r((size_t)nq * star_bits_words(n_cust, nq) * 4);
+}
+
+size_t star_workspace_bound(int32_t n_rows, int32_t nq) {
+  // star_workspace_bytes(n_prod, n_cust, nq) for any n_prod, n_cust <= n_rows: the bitmaps of every customer
+  // row take at most the budget when they are built, the LDS-prefix bitmaps otherwise
+  auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t full = (size_t)nq * (size_t)star_bits_stride(n_rows) * 4;
+  const size_t prefix = (size_t)nq * (size_t)star_bits_stride(n_rows < kStarMaxCustHot ? n_rows : kStarMaxCustHot) * 4;
+  const size_t bits = full < kStarFullBitsBytes ? full : kStarFullBitsBytes;
+  return r((size_t)n_rows * 4) + r(seg_padded(n_rows) + 16) + r((size_t)(nq + 1) * 4) + r(16) +
+         r(bits > prefix ? bits : prefix);
 }
 
 hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t *qstart, const int32_t *qlt,
@@ -390,7 +424,9 @@ hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t
   uint32_t *counter = (uint32_t *)w;
   w += r(16);
   uint32_t *cbits = (uint32_t *)w;  // nq bitmaps of cstride words (16-byte aligned)
-  const int32_t cstride = star_bits_stride(tc);
+  const bool full = star_full_bits(n_cust, nq);
+  const int32_t bit_rows = full ? n_cust : tc;  // rows every bitmap covers
+  const int32_t cstride = star_bits_stride(bit_rows);
   if (tc < 0 || tc > n_cust || tc > kStarMaxCustHot) return hipErrorInvalidValue;
 
   StageTimer st = stage_begin("star_prep", s);
@@ -400,8 +436,8 @@ hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t
   hipLaunchKernelGGL(star_pack_kernel, dim3((int)(g > 0 ? g : 1)), dim3(256), 0, s, price, cat, n_prod, pwords, attr,
                      n_cust, cwords, attr_padded);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess && tc > 0) {
-    const int32_t n_words = (tc + 31) / 32;
+  if (e == hipSuccess && bit_rows > 0) {
+    const int32_t n_words = (int32_t)(((int64_t)bit_rows + 31) / 32);
     const dim3 grid((n_words + kBitsThreads - 1) / kBitsThreads, (nq + kBitsQueries - 1) / kBitsQueries);
     hipLaunchKernelGGL(star_bits_kernel, grid, dim3(kBitsThreads), 0, s, reinterpret_cast<const uint4 *>(cwords),
                        n_words, qlt, nq, cstride, cbits);
@@ -415,9 +451,10 @@ hipError_t launch_star(const int32_t *pkeys, const int32_t *ukeys, const int64_t
   stage_end(st, s);
   if (e != hipSuccess) return e;
   const size_t lds = star_lds_bytes(tp, tc, nq);
-  allow_lds(star_batch_kernel, lds);
+  auto kern = full ? star_batch_kernel<true> : star_batch_kernel<false>;
+  allow_lds(kern, lds);
   st = stage_begin("star_batch", s);
-  hipLaunchKernelGGL(star_batch_kernel, dim3(blocks), dim3(kStarThreads), lds, s, pkeys, ukeys, qstart, qlt, nq,
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kStarThreads), lds, s, pkeys, ukeys, qstart, qlt, nq,
                      tile_start, counter, tile_rows, pwords, n_prod, tp, (const uint32_t *)cwords, n_cust, tc, price,
                      cat, cbits, cstride, out_sum, out_cnt, flag);
   e = hipGetLastError();

@@ -248,14 +248,18 @@ def test_star_rejects(lib, fn, kw, code):
 
 
 def test_star_workspace_holds_the_customer_bitmaps(lib):
-    # one bitmap of min(n_cust, 2^20) bits per query on top of the product words and segment copy
+    # one bitmap per query over every customer row while all of them fit 1 GiB, on top of the product words and
+    # the segment copy
     small = lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 1, 2_000_000)
     big = lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 65, 2_000_000)
-    assert big - small >= 64 * (1 << 20) // 8
-    assert big - small < 64 * (1 << 20) // 8 + 4096
-    # below 2^20 customers the bitmap is as long as the dimension
+    assert 64 * 2_000_000 // 8 <= big - small < 64 * 2_000_000 // 8 + 4096
     d = lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 9, 100_000) - lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 1, 100_000)
     assert 8 * 100_000 // 8 <= d < 8 * 100_000 // 8 + 2048
+    # beyond the budget the sizing bound is the budget itself: every call with at most this many rows in either
+    # dimension fits, whichever bitmaps it builds
+    base = lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 0, 2_500_000)
+    over = lib.skew_workspace_bytes(skew.SKEW_OP_STAR, 4096, 2_500_000) - base
+    assert (1 << 30) <= over < (1 << 30) + 4096 * 4 + 4096
 
 
 def _join_noalloc(lib, **kw):

@@ -146,6 +146,39 @@ def test_star_autotune_signed(signed):
     check(skew.star_join_batch(signed["skew"], best), signed["want"])
 
 
+@pytest.fixture(scope="module")
+def many_cust():
+    """4096 queries (the most a batch takes) of 0-299 rows over 2.5e6 customers: bitmaps of every customer row
+    for every query would take 1.28 GB, over the library's 1 GiB budget, so cold customer rows gather their
+    segments instead of a bit."""
+    k, n_prod, n_cust, nq = 7, 50_000, 2_500_000, 4096
+    rng = np.random.default_rng(77)
+    sizes = rng.integers(0, 300, nq).astype(np.int64)
+    lt = rng.integers(-5, 106, nq).astype(np.int32)
+    say(f"star many-query batch nq={nq} n_cust={n_cust} rows={int(sizes.sum())}")
+    h = W.host_star_inputs(k, n_prod, n_cust, sizes)
+    start = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    want = [oracle.star_join(h["prod"][a:b], h["cust"][a:b], h["price"], h["category"], h["cust_attr"], lt[q])
+            for q, (a, b) in enumerate(zip(start[:-1], start[1:]))]
+    ident = skew.StarBatch(to_dev(h["prod"]), to_dev(h["cust"]), to_dev(start), to_dev(lt), to_dev(h["price"]),
+                           to_dev(h["category"]), to_dev(h["cust_attr"]))
+    Lp = skew.build_skew_layout(ident.prod_keys, n_prod, ident.price, ident.category)
+    Lc = skew.build_skew_layout(ident.cust_keys, n_cust, None, ident.segment)
+    sk = skew.StarBatch(Lp.fact_recoded, Lc.fact_recoded, ident.query_start, ident.query_cust_lt, Lp.price,
+                        Lp.category, Lc.category)
+    return dict(identity=ident, skew=sk, want=want, nq=nq, n_cust=n_cust)
+
+
+@pytest.mark.parametrize("tun", [None, (-1, 1 << 20, 1024, 0), (100, 0, 4096, 3)], ids=str)
+@pytest.mark.parametrize("layout", ["skew", "identity"])
+def test_star_many_queries_segment_gathers(many_cust, tun, layout):
+    say(f"star many queries, 2.5e6 customers, {layout} tuning={tun}")
+    b = many_cust
+    ws = skew.star_workspace(b[layout])
+    assert ws.numel() < b["nq"] * b["n_cust"] // 8  # no room for bitmaps of every row
+    check(skew.star_join_batch(b[layout], None if tun is None else skew.StarTuning(*tun), ws=ws), b["want"])
+
+
 def test_star_autotune(batch):
     say("star autotune")
     best, ms = skew.star_join_autotune(batch["skew"])
