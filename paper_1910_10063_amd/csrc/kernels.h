@@ -102,6 +102,7 @@ int32_t group_max_hot_groups(const DeviceInfo &dev);  // single pass
 size_t group_split_lds_bytes(int32_t hot_groups, int32_t slices);
 int32_t group_split_max_hot_groups(int32_t slices, const DeviceInfo &dev);  // partitioned form
 GroupPlan group_plan(int64_t n_fact, int32_t n_groups, const DeviceInfo &dev);
+int32_t group_narrow_slices(const GroupPlan &pl);  // record slices of the shared table (0: no records)
 size_t group_partition_bytes(const GroupPlan &pl);
 
 // part_ws/part_bytes: optional workspace for the partitioned form (NULL: single pass).

@@ -814,8 +814,10 @@ int skew_group_choose(const uint32_t *counts_by_rank, int32_t n_groups, int64_t 
   const hipStream_t s = (hipStream_t)stream;
   const skew::DeviceInfo pdev = part_device(dev);
   const skew::GroupPlan pl = skew::group_plan(n_fact, n_groups, pdev);
-  const bool can_partition = n_fact >= skew::kPartitionMinFact && pl.slices <= skew::kMaxSlices;
-  int32_t cap = can_partition ? skew::group_split_max_hot_groups(pl.slices, dev) : skew::group_max_hot_groups(dev);
+  // the launch's shared slice table: record slices and pair slices
+  const int32_t Q = pl.slices + skew::group_narrow_slices(pl);
+  const bool can_partition = n_fact >= skew::kPartitionMinFact && pl.slices > 0 && Q <= skew::kMaxSlices;
+  int32_t cap = can_partition ? skew::group_split_max_hot_groups(Q, dev) : skew::group_max_hot_groups(dev);
   if (cap > n_groups) cap = n_groups;
   std::vector<uint64_t> prefix;
   if (int rc = host_prefix(counts_by_rank, cap, prefix, s)) return rc;
