@@ -445,9 +445,10 @@ int skew_profile_report(char *names, int names_bytes, float *ms, int *calls, int
  * there are fewer slices); the single pass holds fewer (12 bytes per group). */
 int32_t skew_max_hot_rows(int32_t group_by_category);
 /* The hot prefix fk_join_aggregate uses for these arguments (hot_rows as the
- * call takes it, workspace_bytes as passed to it).  Its partitioned form
- * shares LDS between the prefix and the buckets of cold keys, so it may use
- * less than skew_max_hot_rows; a negative code on bad arguments. */
+ * call takes it, workspace_bytes as passed to it): hot_rows clamped to
+ * skew_max_hot_rows and n_rows; with SKEW_HOT_AUTO, the single pass over a
+ * small input takes a shorter prefix (a workgroup would copy more rows than
+ * it looks up).  A negative code on bad arguments. */
 int32_t skew_join_hot_rows(int64_t n_fact, int32_t n_rows, int32_t group_by_category, int32_t hot_rows,
                            size_t workspace_bytes);
 int32_t skew_max_hot_groups(void);

@@ -447,16 +447,18 @@ def test_join_dimension_columns_at_any_alignment(F, poff, coff):
 
 
 # ---------------------------------------------------------------------------
-# Cold-key buckets of the partitioned join under inputs that defeat the
-# bucket plan: keys sorted (every tile falls into a few slices), every key
+# The partitioned join under key orders far from a shuffled Zipf column:
+# keys sorted (each workgroup's cold keys fall into a few slices), every key
 # in one slice, and runs of hot keys between runs of keys spread over all
-# slices.  Keys that find no room are gathered; every answer stays exact.
+# slices.  With prefixes below 2048 rows the slice-0 counts of pass 1 and the
+# scatter's slice-0 ranks are combined per slot where slice 0 is dense, which
+# these orders switch on for some workgroups and off for others.
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("shape", ["sorted", "one_slice", "runs"])
-def test_join_bucket_overflow_inputs(shape):
+def test_join_adversarial_key_orders(shape):
     rng = np.random.default_rng({"sorted": 61, "one_slice": 62, "runs": 63}[shape])
     N, F = 1_000_000, (1 << 22) + 777
-    say(f"join buckets shape={shape} N={N} F={F}")
+    say(f"join key order {shape} N={N} F={F}")
     price = rng.integers(1, 10001, N).astype(np.int32)
     cat = rng.integers(0, 16, N).astype(np.int8)
     if shape == "sorted":
