@@ -296,9 +296,10 @@ def main():
         result["single_pass"] = {"skew_tuples_per_s": F / (ms_sp * 1e-3), "identity_tuples_per_s": F / (ms_sp_i * 1e-3)}
         del single_ws
     if not args.no_extras:
-        # hot-prefix sweep, up to the LDS capacity (a larger t is clamped to it)
+        # hot-threshold sweep: up to the LDS capacity every hot row is read from LDS; past it (64K, 128K, 256K)
+        # the rows between the capacity and t are warm, gathered in pass 1 through the caches
         sweep_t = []
-        for t in (0, 4096, 8192, 16384, 32768, skew.SKEW_HOT_AUTO):
+        for t in (0, 4096, 8192, 16384, 32768, skew.SKEW_HOT_AUTO, 65536, 131072, 262144):
             ms = timed(query(Cp, pp, cp, t), max(K // 2, 10), 1, stream)
             used = skew.join_hot_rows(F, N, True, t, ws=jws)
             sweep_t.append({"hot_rows": t, "hot_rows_used": used, "ms": round(ms, 4), "tuples_per_s": F / (ms * 1e-3),

@@ -146,10 +146,15 @@ int append_skew_layout(int32_t n_old, int32_t n_new, int32_t *perm, int32_t *ran
  *                         (signed compare; cat_lt >= 128 means no filter).
  *   group_by_category     0: one output group; 1: 16 groups, group = category,
  *                         rows with category outside [0, 16) in no group.
- *   hot_rows              t: dimension rows [0, t) are copied into LDS once per
- *                         workgroup and read from there (t is clamped to the
- *                         LDS capacity); 0 = every row read from global memory
- *                         (the identity-layout method); SKEW_HOT_AUTO.
+ *   hot_rows              t: dimension rows [0, t) are hot (Section 4.2): the
+ *                         first min(t, skew_max_hot_rows) of them are copied
+ *                         into LDS once per workgroup and read from there; in
+ *                         the partitioned form the hot rows past that capacity
+ *                         are gathered from global memory (through the caches)
+ *                         in pass 1, and the single pass clamps t to the
+ *                         capacity.  0 = every row read from global memory
+ *                         (the identity-layout method); SKEW_HOT_AUTO: the LDS
+ *                         capacity.
  *   out_sum, out_count    out: int64[1] or int64[16].
  *   workspace             >= skew_workspace_bytes(SKEW_OP_JOIN_SINGLE_PASS, ...);
  *                         with skew_workspace_bytes(SKEW_OP_JOIN, n_fact, n_rows)
@@ -444,11 +449,12 @@ int skew_profile_report(char *names, int names_bytes, float *ms, int *calls, int
  * of the partitioned group-by (8 bytes per group; it may hold a few more when
  * there are fewer slices); the single pass holds fewer (12 bytes per group). */
 int32_t skew_max_hot_rows(int32_t group_by_category);
-/* The hot prefix fk_join_aggregate uses for these arguments (hot_rows as the
- * call takes it, workspace_bytes as passed to it): hot_rows clamped to
- * skew_max_hot_rows and n_rows; with SKEW_HOT_AUTO, the single pass over a
- * small input takes a shorter prefix (a workgroup would copy more rows than
- * it looks up).  A negative code on bad arguments. */
+/* The hot threshold fk_join_aggregate uses for these arguments (hot_rows as
+ * the call takes it, workspace_bytes as passed to it): hot_rows clamped to
+ * n_rows, and to skew_max_hot_rows in the single pass; with SKEW_HOT_AUTO,
+ * the LDS capacity, and for the single pass over a small input a shorter
+ * prefix (a workgroup would copy more rows than it looks up).  A negative
+ * code on bad arguments. */
 int32_t skew_join_hot_rows(int64_t n_fact, int32_t n_rows, int32_t group_by_category, int32_t hot_rows,
                            size_t workspace_bytes);
 int32_t skew_max_hot_groups(void);

@@ -255,20 +255,23 @@ __global__ __launch_bounds__(kJoinThreads) void join_kernel(const int32_t *__res
 }
 
 // ---------------------------------------------------------------------------
-// Partitioned form, pass 1: keys below t are resolved from LDS; every other
-// key inside the dimension is appended to this workgroup's segment of the
-// cold buffer and counted in its slice ((k - t) >> wshift).  Workgroup b
-// owns a contiguous range of the column, so its segment needs no more slots
-// than the rows it reads.  With TAIL, the slices end at tail_start (they are
-// at most kMaxSlices) and keys from there to the end of the dimension, the
-// coldest ones, are gathered from global memory as in the single pass.
+// Partitioned form, pass 1: keys below t_lds are resolved from LDS; keys in
+// [t, tail_start) are appended to this workgroup's segment of the cold
+// buffer and counted in their slice ((k - t) >> wshift).  Workgroup b owns a
+// contiguous range of the column, so its segment needs no more slots than
+// the rows it reads.  With GATHER, the other keys inside the dimension are
+// gathered from global memory as in the single pass: the warm rows
+// [t_lds, t) of a threshold t beyond the LDS capacity (hot in the paper's
+// sense, held by the caches instead of LDS), and the tail [tail_start,
+// n_rows) of a dimension with more cold rows than kMaxSlices slices.
 // ---------------------------------------------------------------------------
 struct Tail {
   uint32_t start;  // first row past the slices (n_rows without a tail)
   rsrc_t words;    // all dimension words, range-checked
+  uint32_t t_lds;  // rows [0, t_lds) are in LDS; rows [t_lds, t) are gathered
 };
 
-template <int GROUPS, int V, bool GUARD, bool TAIL>
+template <int GROUPS, int V, bool GUARD, bool GATHER>
 __device__ __forceinline__ void join_split_batch(JoinCtx<GROUPS> &c, const ColdSink &o, rsrc_t seg,
                                                  const uint32_t *hot, uint32_t tclamp, const Tail &tail,
                                                  const i32x4 (&x)[V], const bool (&valid)[V]) {
@@ -282,15 +285,15 @@ __device__ __forceinline__ void join_split_batch(JoinCtx<GROUPS> &c, const ColdS
 #pragma unroll
   for (int i = 0; i < 4 * V; ++i) {
     const bool ok = !GUARD || valid[i / 4];
-    const bool h = ok && k[i] < o.t;
-    cold[i] = ok && !h && k[i] < (TAIL ? tail.start : c.n_rows);
+    const bool h = ok && k[i] < (GATHER ? tail.t_lds : o.t);
+    cold[i] = GATHER ? ok && k[i] >= o.t && k[i] < tail.start : ok && !h && k[i] < c.n_rows;
     c.bad |= ok && k[i] >= c.n_rows;
     const uint32_t wl = hot[k[i] < tclamp ? k[i] : tclamp];
     w[i] = h ? wl : kValid;
-    if (TAIL) {  // out-of-range index for every other key: no memory traffic
-      const bool tl = ok && k[i] >= tail.start && k[i] < c.n_rows;
-      const uint32_t wg = buffer_load_record(tail.words, (int32_t)(tl ? k[i] : 0xFFFFFFFFu), 0, 0, 0);
-      w[i] = tl ? wg : w[i];
+    if (GATHER) {  // warm and tail keys; an out-of-range index for every other key: no memory traffic
+      const bool gl = ok && !h && !cold[i] && k[i] < c.n_rows;
+      const uint32_t wg = buffer_load_record(tail.words, (int32_t)(gl ? k[i] : 0xFFFFFFFFu), 0, 0, 0);
+      w[i] = gl ? wg : w[i];
     }
   }
   uint32_t all = kValid;
@@ -308,22 +311,23 @@ template <int GROUPS>
 __device__ __forceinline__ void join_split_one(JoinCtx<GROUPS> &c, const ColdSink &o, rsrc_t seg,
                                                const uint32_t *hot, uint32_t tclamp, const Tail &tail, bool valid,
                                                uint32_t k) {
-  const bool h = valid && k < o.t;
-  const bool tl = valid && k >= tail.start && k < c.n_rows;
-  const uint32_t wg = buffer_load_record(tail.words, (int32_t)(tl ? k : 0xFFFFFFFFu), 0, 0, 0);
-  const uint32_t w = h ? hot[k < tclamp ? k : tclamp] : (tl ? wg : kValid);
+  const bool h = valid && k < tail.t_lds;
+  const bool cold = valid && k >= o.t && k < tail.start;
+  const bool gl = valid && !h && !cold && k < c.n_rows;  // warm or tail
+  const uint32_t wg = buffer_load_record(tail.words, (int32_t)(gl ? k : 0xFFFFFFFFu), 0, 0, 0);
+  const uint32_t w = h ? hot[k < tclamp ? k : tclamp] : (gl ? wg : kValid);
   c.bad |= valid && k >= c.n_rows;
   join_add(c, w);
   if (!w) join_slow(c, k);
   const uint32_t kk[1] = {k};
-  const bool cd[1] = {valid && !h && k < tail.start};
+  const bool cd[1] = {cold};
   cold_append(o, kk, cd, [&](int, int32_t idx) { buffer_store_record((int32_t)k, seg, idx, 0, 0, 0); });
 }
 
-template <int GROUPS, bool TAIL>
+template <int GROUPS, bool GATHER>
 __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
     const int32_t *__restrict__ keys, int64_t n, const uint32_t *__restrict__ words, int32_t n_rows, int32_t t_lds,
-    int32_t P, int32_t wshift, int32_t tail_start, const int32_t *__restrict__ price, const int8_t *__restrict__ cat, int32_t cat_lt,
+    int32_t t, int32_t P, int32_t wshift, int32_t tail_start, const int32_t *__restrict__ price, const int8_t *__restrict__ cat, int32_t cat_lt,
     int64_t *__restrict__ out_sum, int64_t *__restrict__ out_cnt, int32_t *flag, int32_t *__restrict__ cold_seg,
     int64_t seg_cap, uint32_t *__restrict__ seg_count, uint32_t *__restrict__ hist) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -344,14 +348,14 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
   ColdSink o;
   o.count = lcount;
   o.hist = lhist;
-  o.t = (uint32_t)t_lds;
+  o.t = (uint32_t)t;  // first partitioned row
   o.wshift = wshift;
   o.sink = (uint32_t)P + lane_id();
   // with no or a small hot prefix, slice 0 of a frequency-ordered layout takes most cold keys: its lanes are
   // counted once per slot instead of queueing on one counter
-  o.combine0 = t_lds < kCombineBelow;
+  o.combine0 = t < kCombineBelow;
   const uint32_t tclamp = t_lds > 0 ? (uint32_t)t_lds - 1 : 0u;
-  const Tail tail{(uint32_t)tail_start, record_buffer(words, (uint32_t)n_rows)};
+  const Tail tail{(uint32_t)tail_start, record_buffer(words, (uint32_t)n_rows), (uint32_t)t_lds};
 
   // Contiguous range of key vectors per workgroup; block 0 takes the scalar
   // head, the last block the scalar tail.
@@ -382,12 +386,12 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
   while (base < full_end) {
     int64_t nxt = base + tile_vecs;
     load_tile(xb, nxt < full_end ? nxt : base);
-    join_split_batch<GROUPS, kJoinVecs, false, TAIL>(c, o, seg, hot, tclamp, tail, xa, all_valid);
+    join_split_batch<GROUPS, kJoinVecs, false, GATHER>(c, o, seg, hot, tclamp, tail, xa, all_valid);
     base = nxt;
     if (base >= full_end) break;
     nxt = base + tile_vecs;
     load_tile(xa, nxt < full_end ? nxt : base);
-    join_split_batch<GROUPS, kJoinVecs, false, TAIL>(c, o, seg, hot, tclamp, tail, xb, all_valid);
+    join_split_batch<GROUPS, kJoinVecs, false, GATHER>(c, o, seg, hot, tclamp, tail, xb, all_valid);
     base = nxt;
   }
   if (full_end < ve) {  // last partial tile
@@ -399,7 +403,7 @@ __global__ __launch_bounds__(kJoinThreads) void join_split_kernel(
       valid[u] = vi < ve;
       x[u] = valid[u] ? load_stream4(vk + vi) : i32x4{0, 0, 0, 0};
     }
-    join_split_batch<GROUPS, kJoinVecs, true, TAIL>(c, o, seg, hot, tclamp, tail, x, valid);
+    join_split_batch<GROUPS, kJoinVecs, true, GATHER>(c, o, seg, hot, tclamp, tail, x, valid);
   }
   __syncthreads();
   if (threadIdx.x == 0) seg_count[blockIdx.x] = *lcount < seg_cap ? *lcount : (uint32_t)seg_cap;
@@ -573,13 +577,18 @@ size_t join_partition_bytes(const JoinPlan &pl) {
 int32_t join_hot_rows_used(int64_t n_fact, int32_t n_rows, int32_t by_cat, int32_t hot_rows, size_t part_bytes,
                            const DeviceInfo &dev, bool *partitioned) {
   const int groups = by_cat ? 16 : 1;
-  int32_t t = hot_rows;
   const int32_t cap = join_max_hot_rows(groups, dev);
-  if (t < 0 || t > cap) t = cap;
+  int32_t t = hot_rows < 0 ? cap : hot_rows;
   if (t > n_rows) t = n_rows;
-  const JoinPlan pl = join_plan(n_fact, n_rows, t, groups, dev);
-  *partitioned = part_bytes > 0 && n_fact >= kPartitionMinFact && pl.slices > 0 &&
+  const int32_t tc = t < cap ? t : cap;
+  // the workspace holds the partitioned form's buffers for the threshold clamped to LDS (they do not grow
+  // with a warm range); a threshold past the last row leaves nothing to partition
+  const JoinPlan pl = join_plan(n_fact, n_rows, tc, groups, dev);
+  *partitioned = part_bytes > 0 && n_fact >= kPartitionMinFact && pl.slices > 0 && t < n_rows &&
                  part_bytes >= join_partition_bytes(pl);
+  // rows past the LDS capacity stay hot only in the partitioned form (gathered in pass 1); the single pass
+  // gathers every key past its LDS prefix anyway
+  if (!*partitioned) t = tc;
   if (!*partitioned && hot_rows < 0) {
     // Every workgroup of the single pass copies the prefix into LDS: for a small input, a prefix much longer
     // than half the keys a workgroup reads costs more to stage than its lookups save (8192 rows at 1e6-4e6
@@ -607,6 +616,8 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
   if (e != hipSuccess || n_fact == 0) return e;
   bool partitioned = false;
   const int32_t t = join_hot_rows_used(n_fact, n_rows, by_cat, hot_rows, part_ws ? part_bytes : 0, dev, &partitioned);
+  const int32_t cap = join_max_hot_rows(groups, dev);
+  const int32_t t_lds = t < cap ? t : cap;  // rows [t_lds, t) are warm: gathered in pass 1
   const JoinPlan pl = join_plan(n_fact, n_rows, t, groups, dev);
   if (!partitioned) {
     const size_t lds = join_lds_bytes(groups, t);
@@ -651,23 +662,23 @@ hipError_t launch_join(const int32_t *keys, int64_t n_fact, const int32_t *price
   ws += r((size_t)pl.blocks * 4);
   tab.slice_off = (uint32_t *)ws;
 
-  const size_t lds1 = join_lds_bytes(groups, t) + (size_t)(pl.slices + kWave + 4) * 4;
+  const size_t lds1 = join_lds_bytes(groups, t_lds) + (size_t)(pl.slices + kWave + 4) * 4;
   const size_t lds3 = (groups == 16 ? (size_t)kJoinBinRows * kWave * 8 : 0) + ((size_t)4 << pl.wshift) +
                       (size_t)(pl.slices + 1) * 4;
   // keys past the last slice (dimensions of more than kMaxSlices slices) are gathered in pass 1
   const int64_t tail_row = (int64_t)t + ((int64_t)pl.slices << pl.wshift);
   const int32_t tail_start = tail_row < n_rows ? (int32_t)tail_row : n_rows;
-  const bool tail = tail_start < n_rows;
-  auto split_kernel = groups == 16 ? (tail ? join_split_kernel<16, true> : join_split_kernel<16, false>)
-                                   : (tail ? join_split_kernel<1, true> : join_split_kernel<1, false>);
+  const bool gather = tail_start < n_rows || t_lds < t;
+  auto split_kernel = groups == 16 ? (gather ? join_split_kernel<16, true> : join_split_kernel<16, false>)
+                                   : (gather ? join_split_kernel<1, true> : join_split_kernel<1, false>);
   allow_lds(split_kernel, lds1);
   if (groups == 16) allow_lds(join_slice_kernel<16>, lds3);
   else allow_lds(join_slice_kernel<1>, lds3);
   for (int64_t off = 0; off < n_fact; off += pl.round) {
     const int64_t n = n_fact - off < pl.round ? n_fact - off : pl.round;
     st = stage_begin("join_split", s);
-    hipLaunchKernelGGL(split_kernel, dim3(pl.blocks), dim3(kJoinThreads), lds1, s, keys + off, n, words, n_rows, t,
-                       pl.slices, pl.wshift, tail_start, price, cat, cat_lt, out_sum, out_cnt, flag, seg, pl.seg_cap,
+    hipLaunchKernelGGL(split_kernel, dim3(pl.blocks), dim3(kJoinThreads), lds1, s, keys + off, n, words, n_rows,
+                       t_lds, t, pl.slices, pl.wshift, tail_start, price, cat, cat_lt, out_sum, out_cnt, flag, seg, pl.seg_cap,
                        tab.seg_count, tab.hist);
     e = hipGetLastError();
     stage_end(st, s);

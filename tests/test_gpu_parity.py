@@ -109,7 +109,8 @@ def test_join_by_category_reduced(s):
     check_layout(L, ref)
     for op in (skew.SKEW_OP_JOIN, skew.SKEW_OP_JOIN_SINGLE_PASS):  # partitioned and single-pass forms
         ws = skew.workspace(op, F, N, DEV)
-        for t in (0, 4096, 32768, skew.SKEW_HOT_AUTO):
+        # past the LDS capacity the partitioned form gathers the warm rows [capacity, t) in pass 1
+        for t in (0, 4096, 32768, skew.SKEW_HOT_AUTO, 65_536, 262_144, 999_999, 1_000_000):
             s_, c_ = skew.fk_join_aggregate(L.fact_recoded, L.price, L.category, 16, True, hot_rows=t, ws=ws)
             assert (host(s_) == es).all() and (host(c_) == ec).all(), ("skew", op, t)
         s_, c_ = skew.fk_join_aggregate(d["fact"], d["price"], d["category"], 16, True, hot_rows=0, ws=ws)
@@ -403,7 +404,8 @@ def test_generator_device_matches_host():
 
 def test_partitioned_join_with_gathered_tail():
     """A dimension larger than the slices can cover (1024 slices of 32768 rows past the hot prefix): keys past the
-    last slice are gathered in pass 1, the rest partitioned; escapes and odd categories in both parts."""
+    last slice are gathered in pass 1, the rest partitioned; escapes and odd categories in both parts.  Thresholds
+    past the LDS capacity add a warm range gathered in pass 1 before the slices."""
     say("partitioned join with a gathered tail")
     rng = np.random.default_rng(77)
     N, F = 40_000_000, (1 << 22) + 12_345
@@ -419,7 +421,7 @@ def test_partitioned_join_with_gathered_tail():
     fd, pd, cd = to_dev(fact), to_dev(price), to_dev(cat)
     for by_cat, cat_lt in ((True, 16), (False, 9)):
         es, ec = oracle.fk_join_aggregate(fact, price, cat, cat_lt, by_cat)
-        for t in (0, 7, skew.SKEW_HOT_AUTO):
+        for t in (0, 7, skew.SKEW_HOT_AUTO, 300_000, 6_000_000):
             s, c = skew.fk_join_aggregate(fd, pd, cd, cat_lt, by_cat, hot_rows=t, ws=ws)
             assert (host(s) == es).all() and (host(c) == ec).all(), (by_cat, t)
     assert skew.query_status(ws) == skew.SKEW_OK
