@@ -76,7 +76,7 @@ constexpr int kGroupThreads = 1024;
 constexpr int kGroupCopies = 16;        // hottest ranks kept as per-lane copies (Section 4.2.2)
 constexpr int kJoinSliceShift = 15;     // 32768 dimension words per LDS slice
 constexpr int kGroupSliceShift = 13;    // 8192 groups per LDS slice
-constexpr int64_t kMaxRound = 1LL << 28;         // rows per round of the partitioned form
+constexpr int64_t kMaxRound = 1LL << 28;         // keys per round of the partitioned key histogram
 constexpr int64_t kJoinMaxRound = 1LL << 29;     // the join's rounds (fewer copies of each slice in pass 3)
 constexpr int64_t kGroupMaxRound = 1LL << 29;    // the group-by's rounds
 constexpr int64_t kPartitionMinFact = 1LL << 22;  // below this the single pass is used
