@@ -45,6 +45,8 @@ def tables():
 def requests(seed):
     arr = serving.poisson_arrivals(200.0, 0.4, seed)
     reqs = serving.make_requests(arr, F, 10_000, 4_000_000, seed)
+    for r in reqs[:6]:  # a burst: the first six arrive together, so six slots run them side by side
+        r.arrival = reqs[5].arrival
     for r in reqs:  # the request's own outputs, filled with a value no aggregate takes
         r.out = (torch.full((M,), -7, dtype=torch.int64, device=DEV), torch.full((M,), -7, dtype=torch.int64,
                                                                                    device=DEV))
@@ -87,9 +89,10 @@ def test_alone_equals_mix_and_oracle(tables):
         es, ec = expected(h, r)
         np.testing.assert_array_equal(ms, es, err_msg=f"request {rid}: SUM vs oracle")
         np.testing.assert_array_equal(mc, ec, err_msg=f"request {rid}: COUNT vs oracle")
-    # overlap: some request was admitted before an earlier one finished
+    # overlap: the burst is admitted in one pass of the loop, before any of it is harvested
     rs = sorted(mix.values(), key=lambda r: r.admitted)
     assert any(b.admitted < a.done for a, b in zip(rs, rs[1:]))
+    assert all(mix[i].admitted < min(mix[j].done for j in range(6)) for i in range(6))
 
 
 def test_drift_rebuild_keeps_answers(tables):
