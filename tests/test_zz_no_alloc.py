@@ -3,7 +3,8 @@
 Two calls in a row on one stream, the second with a smaller input (fewer
 dimension rows, fewer fact keys, other data), each compared element by
 element with fk_join_aggregate (the entry point with a workspace) on the same
-inputs and with the oracle.  A dimension larger than the library's fixed
+inputs and with the oracle.  The call captured in a HIP graph gives the
+oracle's answer on every replay.  A dimension larger than the library's fixed
 scratch is rejected on the host.
 """
 import sys
@@ -61,3 +62,29 @@ def test_noalloc_rejects_a_dimension_larger_than_its_scratch():
     with pytest.raises(skew.SkewError) as e:
         skew.fk_join_aggregate_noalloc(keys, price, cat, 16, True, out)
     assert e.value.code == skew.SKEW_EINVAL
+
+
+def test_noalloc_replayed_from_a_hip_graph():
+    """The entry point captured in a HIP graph (what a caller that cannot allocate does with it): every replay,
+    with eager work and synchronisations between them, equals the oracle."""
+    N, F = 100_000, 2_000_003
+    say(f"noalloc join in a HIP graph N={N} F={F}")
+    h, d = inputs(2, N, F, 1.0)
+    L = skew.build_skew_layout(d["fact"], N, d["price"], d["category"])
+    es, ec = oracle.fk_join_aggregate(h["fact"], h["price"], h["category"], 16, True)
+    out = (torch.empty(16, dtype=torch.int64, device=DEV), torch.empty(16, dtype=torch.int64, device=DEV))
+    skew.fk_join_aggregate_noalloc(L.fact_recoded, L.price, L.category, 16, True, out)  # eager first call
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        skew.fk_join_aggregate_noalloc(L.fact_recoded, L.price, L.category, 16, True, out)
+    for i in range(3):
+        out[0].fill_(-1)
+        out[1].fill_(-7)
+        junk = torch.randn(1 << 20, device=DEV).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out[0].cpu().numpy(), es, err_msg=f"sum, replay {i}")
+        np.testing.assert_array_equal(out[1].cpu().numpy(), ec, err_msg=f"count, replay {i}")
+        assert torch.isfinite(junk)
