@@ -567,8 +567,8 @@ def bench_star(K, dev, stream):
 
 def bench_serve(seconds, dev):
     """Serving loop: Poisson arrivals at 200 requests/s of grouped aggregations over row ranges (log-uniform
-    1e5..5e8 rows) of the resident group-by table (5e8 rows, 1e6 groups, Zipf 1.1); slots from a 16 GB memory
-    budget; at 15 s 1e7 rows are inserted (recoded through the current layout, no rebuild); at 30 s a new table
+    1e5..5e8 rows) of the resident group-by table (5e8 rows, 1e6 groups, Zipf 1.1); slots from a 64 GB memory
+    budget (9 GB per slot: the partitioned group-by's workspace for 5e8 rows); at 15 s 1e7 rows are inserted (recoded through the current layout, no rebuild); at 30 s a new table
     version with re-permuted popularity arrives (drift, rebuild)."""
     import torch
 
@@ -581,7 +581,7 @@ def bench_serve(seconds, dev):
     for v, k in ((1, 3), (2, 13)):
         g = W.device_group_inputs(k, M, F, 1.1, device=dev)
         tabs.append(serving.TableVersion(v, g["keys"], g["vals"], M))
-    budget = 16 << 30
+    budget = 64 << 30
     max_rows = F
     slots = serving.plan_slots(budget, max_rows, M)
     srv = serving.Server(tabs[0], slots, max_rows)

@@ -308,7 +308,17 @@ def latency_report(done: list[Request]) -> dict:
     lat = np.array([r.done - r.arrival for r in done]) * 1e3
     rows = sum(r.rows for r in done)
     span = max(r.done for r in done) - min(r.arrival for r in done)
+    # requests in flight at once (admitted, not yet harvested), and how many were admitted while another one ran
+    ev = sorted([(r.admitted, 1) for r in done] + [(r.done, -1) for r in done], key=lambda e: (e[0], e[1]))
+    depth = peak = 0
+    overlapped = 0
+    for _, d in ev:
+        if d > 0 and depth > 0:
+            overlapped += 1
+        depth += d
+        peak = max(peak, depth)
     return {"requests": len(done), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "rows": int(rows), "tuples_per_s": rows / span if span > 0 else 0.0,
             "served_on_skew": sum(r.layout == "skew" for r in done),
-            "served_on_identity": sum(r.layout == "identity" for r in done)}
+            "served_on_identity": sum(r.layout == "identity" for r in done),
+            "max_in_flight": peak, "admitted_while_another_ran": overlapped}

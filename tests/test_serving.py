@@ -39,8 +39,18 @@ def test_plan_slots_respects_budget():
 def test_latency_report():
     reqs = [serving.Request(i, 0.001 * i, 0, 100 + i) for i in range(100)]
     for r in reqs:
+        r.admitted = r.arrival
         r.done = r.arrival + 0.002 + (0.01 if r.rid == 99 else 0.0)
         r.layout = "skew" if r.rid % 2 else "identity"
     rep = serving.latency_report(reqs)
     assert abs(rep["p50_ms"] - 2.0) < 1e-9 and rep["p99_ms"] >= 2.0
     assert rep["served_on_skew"] == 50 and rep["rows"] == sum(100 + i for i in range(100))
+
+
+def test_latency_report_counts_requests_in_flight():
+    # A runs over [0, 4), B over [1, 2) inside it, C from 4, when A ends (eighths of a second: exact floats)
+    reqs = [serving.Request(i, a / 8, 0, 10) for i, a in enumerate((0, 1, 4))]
+    for r, (a, d) in zip(reqs, ((0, 4), (1, 2), (4, 5))):
+        r.admitted, r.done, r.layout = a / 8, d / 8, "skew"
+    rep = serving.latency_report(reqs)
+    assert rep["max_in_flight"] == 2 and rep["admitted_while_another_ran"] == 1
