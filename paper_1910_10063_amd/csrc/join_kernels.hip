@@ -213,21 +213,18 @@ __global__ __launch_bounds__(kJoinThreads) void join_kernel(const int32_t *__res
   h.words = record_buffer(words, (uint32_t)n_rows);
   h.t = (uint32_t)t_lds;
   h.tclamp = t_lds > 0 ? (uint32_t)t_lds - 1 : 0u;  // LDS always holds at least one word
-  stage_words(hot, words, 0, t_lds);
-  if (t_lds == 0 && threadIdx.x == 0) hot[0] = 0;
-  __syncthreads();
 
-  const Split4 sp = split4(keys, n);
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid < sp.head) join_single(c, h, keys[gid]);
-  if (gid < n - sp.tail) join_single(c, h, keys[sp.tail + gid]);
-
-  // The prefetch is unconditional (the last one re-reads the current tile) so
+  // Tiles of kJoinVecs vectors per thread while every workgroup gets at least
+  // one; below that (small inputs) one vector per thread, so that all
+  // workgroups share the keys.  The first keys are requested before the
+  // prefix is staged, so that a workgroup waits for both at once.  The tile
+  // prefetch is unconditional (the last one re-reads the current tile) so
   // that every path has the same loads in flight and the wait before a batch
   // covers only that batch's keys.
+  const Split4 sp = split4(keys, n);
   const i32x4 *vk = reinterpret_cast<const i32x4 *>(keys + sp.head);
   const int64_t tile_vecs = (int64_t)kJoinThreads * kJoinVecs;
-  const int64_t ntiles = sp.nvec / tile_vecs;
+  const int64_t ntiles = sp.nvec / tile_vecs >= (int64_t)gridDim.x ? sp.nvec / tile_vecs : 0;
   int64_t tile = blockIdx.x;
   i32x4 xa[kJoinVecs], xb[kJoinVecs];
   auto load_tile = [&](i32x4(&x)[kJoinVecs], int64_t tl) {
@@ -235,7 +232,19 @@ __global__ __launch_bounds__(kJoinThreads) void join_kernel(const int32_t *__res
 #pragma unroll
     for (int u = 0; u < kJoinVecs; ++u) x[u] = load_stream4(p + u * kJoinThreads);
   };
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t vstride = (int64_t)gridDim.x * blockDim.x;
+  int64_t v = ntiles * tile_vecs + gid;  // this thread's first single vector
+  i32x4 x1 = {0, 0, 0, 0};
   if (tile < ntiles) load_tile(xa, tile);
+  else if (v < sp.nvec) x1 = load_stream4(vk + v);
+  stage_words(hot, words, 0, t_lds);
+  if (t_lds == 0 && threadIdx.x == 0) hot[0] = 0;
+  __syncthreads();
+
+  if (gid < sp.head) join_single(c, h, keys[gid]);
+  if (gid < n - sp.tail) join_single(c, h, keys[sp.tail + gid]);
+
   while (tile < ntiles) {
     int64_t nxt = tile + gridDim.x;
     load_tile(xb, nxt < ntiles ? nxt : tile);
@@ -247,8 +256,10 @@ __global__ __launch_bounds__(kJoinThreads) void join_kernel(const int32_t *__res
     join_batch<GROUPS, kJoinVecs>(c, h, xb);
     tile = nxt;
   }
-  for (int64_t v = ntiles * tile_vecs + gid; v < sp.nvec; v += (int64_t)gridDim.x * blockDim.x) {
-    const i32x4 x[1] = {load_stream4(vk + v)};
+  if (ntiles > 0 && v < sp.nvec) x1 = load_stream4(vk + v);
+  for (; v < sp.nvec; v += vstride) {
+    const i32x4 x[1] = {x1};
+    if (v + vstride < sp.nvec) x1 = load_stream4(vk + v + vstride);  // the next vector, while this one is resolved
     join_batch<GROUPS, 1>(c, h, x);
   }
   join_flush(c, flag);
