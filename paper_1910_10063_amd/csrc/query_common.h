@@ -106,7 +106,7 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 __device__ __forceinline__ uint32_t wave_reserve(uint32_t *count, uint32_t n) {
   const uint64_t act = __ballot(1);
   uint32_t base = 0;
-  if (lane_id() == (uint32_t)(__ffsll((unsigned long long)act) - 1)) base = atomicAdd(count, n);
+  if ((uint32_t)lane_id() == (uint32_t)(__ffsll((unsigned long long)act) - 1)) base = atomicAdd(count, n);
   return __builtin_amdgcn_readfirstlane(base);
 }
 
@@ -199,21 +199,8 @@ template <int NC, class Store>
 __device__ __forceinline__ void chunk_drain(const ColdSink &o, WaveChunk<NC> &ch, Store store) {
   if (ch.n == 0) return;
   const uint32_t pos = wave_reserve(o.count, ch.n);
-  store(ch.col, (int32_t)(pos + lane_id()), lane_id() < ch.n);
+  store(ch.col, (int32_t)(pos + lane_id()), (uint32_t)lane_id() < ch.n);
   ch.n = 0;
-}
-
-// Slots k[i] with cold[i] go to the open chunk and are counted in their
-// slice; the other lanes count into their sink word.
-template <int N, int NC, class Store>
-__device__ __forceinline__ void cold_append_dense(const ColdSink &o, WaveChunk<NC> &ch, const uint32_t (&k)[N],
-                                                  const bool (&cold)[N], const uint32_t (&cols)[N][NC],
-                                                  Store store) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    chunk_append(o, ch, cold[i], cols[i], store);
-    lds_add_u32(&o.hist[cold[i] ? (k[i] - o.t) >> o.wshift : o.sink], 1u);
-  }
 }
 
 // ---------------------------------------------------------------------------
