@@ -227,8 +227,8 @@ def main():
 
     stages_skew = per_query(st_skew, KP)
     stages_ident = per_query(st_ident, KP)
-    # Roofline of the whole query (the hot-path table's algorithmic bytes: every fact key once, 4 B, and both
-    # dimension columns once, 5 B per row, plus the 16 x 2 int64 outputs) over the median query time, and,
+    # Roofline of the whole query (its algorithmic bytes: every fact key once, 4 B, and both dimension
+    # columns once, 5 B per row, plus the 16 x 2 int64 outputs) over the median query time, and,
     # beside it, the dominant kernel on its own share: the keys one launch streams, 4 B each.
     dom = max(stages_skew, key=lambda k: stages_skew[k]["ms"])
     launches = stages_skew[dom]["launches"]

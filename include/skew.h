@@ -314,7 +314,7 @@ int cache_model_hit_rate(const uint32_t *counts_by_rank, int32_t n_keys, const i
                          size_t workspace_bytes, void *stream);
 
 /*
- * Batched star join (the batch workload of the hot-path table): many fact
+ * Batched star join: many fact
  * tables, each with a product key and a customer key per row, joined with a
  * product dimension (price, category) and a customer dimension (int8
  * segment).  Query q returns SUM(price) and COUNT(*) grouped by the product's
